@@ -1,0 +1,195 @@
+#!/usr/bin/env python3
+"""Benchmark of the fused NDG RHS + RK4 stage path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 4] [--precision fp64]
+
+A step is one classical RK4 step (four fused RHS + stage launches) over the
+whole mesh of the chosen workload; default: 3-D isothermal Euler, 64^3
+elements, N = 4 (125 nodes per element, 131,072,000 unknowns), FP64, seeded
+solenoidal velocity at Mach 0.1. The state is resident in HBM before the
+timed region. Prints one JSON line:
+
+  value        unknown (DOF) updates per second per RK stage:
+               unknowns * 4 stages * K / timed seconds
+  roofline     the stage kernel's achieved HBM bandwidth from its algorithmic
+               bytes (3.5 state-array passes per launch on average: the RK4
+               schedule reads/writes 2, 4, 5 and 3 arrays in its four stages)
+               over its average launch time from HIP events on its stream;
+               traffic = measured HBM bytes per launch from rocprofv3 counters
+               (profiles/), null when the kernel changed since they were taken
+  cpu_baseline the CPU oracle (FP64, OpenMP) timed on this host on full-mesh
+               RK4 steps of the same workload (a bounded sample, >= 1 step)
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "NDG DOF-updates/s per RK stage + %HBM peak; served solves/s with p50/p99"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, AMD public specification
+PASSES_PER_STEP = {4: 14, 3: 9}
+STAGES = {4: 4, 3: 3}
+KERNEL_SOURCES = ["paper_2510_05254_amd/csrc/dg_stage.hpp"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload: str, precision: str):
+    """Measured HBM bytes per stage launch from profiles/, if the kernel is unchanged."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{precision}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_hash") != kernel_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(w, U0, dt, budget_s: float):
+    """The oracle as it stands, on the host cores, on full-mesh RK4 steps."""
+    import oracle
+    oracle.build(force=False)
+    threads = oracle.get_threads()
+    steps, t0 = 0, time.perf_counter()
+    U = U0
+    while True:
+        U = oracle.step(w.dim, w.N, w.K, w.eq, w.params, U, 4, dt, 1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or steps >= 50:
+            break
+        if el / steps * (steps + 1) > 1.5 * budget_s:
+            break
+    return {"value": w.unknowns * 4 * steps / el, "unit": "DOF-updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{steps} full-mesh RK4 step(s) of {w.name} ({w.unknowns} unknowns), "
+                      f"{el:.1f} s, FP64, OpenMP over elements"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=4)
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--rk", type=int, choices=[3, 4], default=4)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2510_05254_amd import dg
+    from paper_2510_05254_amd import workloads as W
+
+    w = W.config(a.config)
+    prec = dg.DG_FP64 if a.precision == "fp64" else dg.DG_FP32
+    rsize = 8 if prec == dg.DG_FP64 else 4
+    torch.cuda.init()
+    stream = torch.cuda.Stream()
+    s = dg.Solver(w.dim, w.N, w.K, w.eq, w.params, precision=prec, hip_stream=stream.cuda_stream)
+    ax = s.axis_coords()
+    t0 = time.perf_counter()
+    U0 = W.initial_state(w, ax)
+    dt, _ = W.time_step(w, ax, U0)
+    t_ic = time.perf_counter() - t0
+    s.set_state(U0)
+    m0 = s.mass()
+
+    s.step(a.rk, dt, a.warmup)
+    s.synchronize()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    s.step(a.rk, dt, a.steps)
+    ev1.record(stream)
+    ev1.synchronize()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    m1 = s.mass()
+    Ufin = s.get_state()
+    if not np.all(np.isfinite(Ufin)):
+        print("non-finite state after the timed steps", file=sys.stderr)
+        sys.exit(1)
+    del Ufin
+
+    stages = STAGES[a.rk]
+    launches = stages * a.steps
+    ms_step = ms / a.steps
+    value = w.unknowns * stages * a.steps / (ms / 1e3)
+    avg_launch_s = ms / 1e3 / launches
+    alg_bytes = PASSES_PER_STEP[a.rk] / stages * w.unknowns * rsize
+    achieved = alg_bytes / avg_launch_s / 1e9
+    traffic = load_traffic(w.name, a.precision)
+
+    # achievable bandwidth: a plain device-to-device copy of 2 GiB
+    src = torch.empty(1 << 28, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    c1.record()
+    c1.synchronize()
+    copy_gbs = 5 * 2 * src.numel() * 8 / (c0.elapsed_time(c1) / 1e3) / 1e9
+    del src, dst
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == dg.DG_FP64 else "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "dim": w.dim, "N": w.N, "K": list(w.K),
+                   "equation": "advection" if w.eq == 0 else "isothermal_euler",
+                   "rk": a.rk, "unknowns": w.unknowns, "nodes": w.nodes, "dt": dt,
+                   "precision": a.precision},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "kernel": "stage_kernel", "alg_bytes_per_launch": alg_bytes,
+                     "avg_launch_us": avg_launch_s * 1e6},
+        "nodes_per_s": w.nodes * stages * a.steps / (ms / 1e3),
+        "copy_gbps": copy_gbs,
+        "mass_drift": (np.abs(m1 - m0) / np.maximum(np.abs(m0), 1.0)).max(),
+        "ic_seconds": t_ic,
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, U0, dt, a.cpu_budget)
+        out["cpu_baseline"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
+    s.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,166 @@
+/*
+ * dg.h -- C ABI of libdg, the MI355X (gfx950) library that advances nodal
+ * discontinuous Galerkin (NDG) discretisations of periodic linear advection
+ * and isothermal Euler in one, two and three dimensions with explicit
+ * Runge-Kutta schemes.
+ *
+ * Method (Sporykhin & Homann, "Performance of a high-order MPI-Kokkos
+ * accelerated fluid solver", arXiv:2510.05254):
+ *   - the conservation law dU/dt + sum_d dF_d(U)/dx_d = 0 (Sec. 2.1, eq.
+ *     scalar_cons; eqs. advection1d, advection2d, eulerIso2d);
+ *   - tensor-product elements of N+1 Legendre-Gauss-Lobatto nodes per
+ *     direction with the lumped LGL mass (Sec. 2.1, eqs. lagrange_pol,
+ *     lag_coefs), the weak-form evolution equation of Sec. 2.1 and the
+ *     Lax-Friedrichs numerical flux with alpha the largest absolute flux
+ *     eigenvalue of the two traces at each face point (eq. LF);
+ *   - periodic boundaries (Sec. 3.1);
+ *   - the RK schemes of Sec. 2.3: RK3 (read as Heun's third-order method,
+ *     whose coefficients the printed eq. RK3 carries), classical RK4 (eq. RK4)
+ *     and Luther's sixth-order RK6 (eq. RK6);
+ *   - the L2 norm of Sec. 3.1, integrated with the nodal LGL rule.
+ *
+ * Mesh: the periodic unit domain [0,1)^dim with K[d] uniform elements along
+ * direction d, dx_d = 1/K[d]. Element e covers [e_d dx_d, (e_d+1) dx_d] and its
+ * node i along d sits at x = e_d dx_d + (dx_d/2)(xi_i + 1).
+ *
+ * State layout ("canonical", used by every array crossing this ABI):
+ *   u[v * nodes + e * Np + n], Np = (N+1)^dim, nodes = prod(K) * Np,
+ *   e = e_x + K[0] (e_y + K[1] e_z), n = i + (N+1)(j + (N+1) k),
+ * i.e. variable-major, then element (x fastest), then node (x fastest).
+ * Variables: advection (U); isothermal Euler (rho, rho u_1, ..., rho u_dim).
+ * Face nodes are stored once per element (discontinuous representation).
+ *
+ * Ownership: a dg_solver owns its device memory (unless a workspace is passed
+ * to dg_create_ex) and its HIP stream (unless one is passed). The caller owns
+ * every host and device array it passes; the library copies from them before
+ * the call returns (host arrays) or in stream order (device arrays).
+ *
+ * Errors: every entry point returns DG_OK or a negative status; nothing
+ * throws across the ABI. A failed call leaves the solver's state unchanged.
+ * dg_last_error() gives a message for the calling thread's last failure.
+ * Arguments are validated before any device is touched, so invalid arguments
+ * give DG_EINVAL even on a machine without a GPU.
+ *
+ * Threading: one host thread at a time per solver; distinct solvers are
+ * independent.
+ */
+#ifndef DG_H
+#define DG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dg_solver dg_solver;
+
+enum dg_status {
+    DG_OK = 0,
+    DG_EINVAL = -1,   /* invalid argument */
+    DG_ENOMEM = -2,   /* device memory (or the given workspace) too small */
+    DG_EDEVICE = -3,  /* no usable GPU, or a HIP call failed */
+    DG_ENOTSUP = -4,  /* valid request this build does not support */
+    DG_ESTATE = -5    /* call out of order (e.g. stepping before a state is set) */
+};
+
+enum dg_equation { DG_ADVECTION = 0, DG_EULER_ISOTHERMAL = 1 };
+enum dg_rk { DG_RK3 = 3, DG_RK4 = 4, DG_RK6 = 6 };
+enum dg_precision { DG_FP64 = 0, DG_FP32 = 1 };
+
+#define DG_MAX_ORDER 8   /* polynomial degree N ranges over 1..DG_MAX_ORDER */
+
+/* Create a solver on the current HIP device, FP64, own stream, own memory.
+ *   dim       1, 2 or 3
+ *   N         polynomial degree, 1..8 (N+1 LGL nodes per direction)
+ *   K         K[0..dim-1] >= 1, elements per direction (K[d] = 1 is its own
+ *             periodic neighbour)
+ *   equation  DG_ADVECTION: params = a[0..dim-1], the advection velocity
+ *             (finite); DG_EULER_ISOTHERMAL: params = {c_s}, the sound speed
+ *             (finite, > 0)
+ *   out       receives the handle
+ * Returns DG_EINVAL, DG_ENOMEM or DG_EDEVICE on failure. */
+int dg_create(int dim, int N, const int64_t *K, int equation, const double *params,
+              dg_solver **out);
+
+/* dg_create with options:
+ *   precision        DG_FP64 or DG_FP32 (state, RHS and stage updates in that
+ *                    type; L2 and mass reductions always accumulate in FP64)
+ *   hip_stream       a hipStream_t to run on, or NULL for a library stream
+ *   device_workspace device memory of workspace_bytes the library carves its
+ *                    arrays from, or NULL to let the library allocate. With a
+ *                    workspace the library never allocates device memory;
+ *                    its size must be at least dg_workspace_bytes(..., rk)
+ *                    for every rk the caller will step with (DG_ENOMEM from
+ *                    dg_step otherwise). It must outlive the solver. */
+int dg_create_ex(int dim, int N, const int64_t *K, int equation, const double *params,
+                 int precision, void *hip_stream, void *device_workspace,
+                 size_t workspace_bytes, dg_solver **out);
+
+/* Device bytes a solver needs to step with scheme rk (3, 4 or 6). */
+int dg_workspace_bytes(int dim, int N, const int64_t *K, int equation, int precision, int rk,
+                       size_t *bytes);
+
+/* Release the solver (waits for its stream). NULL is accepted. */
+int dg_destroy(dg_solver *h);
+
+/* nvar = number of conserved variables; nodes = prod(K) (N+1)^dim.
+ * A state array holds nvar * nodes doubles. Either pointer may be NULL. */
+int dg_sizes(const dg_solver *h, int *nvar, int64_t *nodes);
+
+/* Node coordinates along one axis: x[e*(N+1) + i], count = K[axis] (N+1). */
+int dg_get_axis_coords(const dg_solver *h, int axis, double *x, int64_t count);
+
+/* Copy a host state (canonical layout, count = nvar * nodes doubles) in.
+ * Synchronous with respect to the host buffer; stream-ordered on the device. */
+int dg_set_state(dg_solver *h, const double *u, int64_t count);
+
+/* As dg_set_state from a device array of count doubles (stream-ordered; the
+ * caller keeps it alive until the solver's stream has passed this point). */
+int dg_set_state_device(dg_solver *h, const void *u_dev, int64_t count);
+
+/* Advance nsteps steps of size dt with scheme rk (DG_RK3, DG_RK4, DG_RK6).
+ * Asynchronous: enqueues nsteps * stages kernel launches on the solver's
+ * stream and returns. dt must be finite and > 0, nsteps >= 0 (0 is a no-op).
+ * DG_ESTATE before the first set_state. No blow-up check is made. */
+int dg_step(dg_solver *h, int rk, double dt, int64_t nsteps);
+
+/* Copy the current state out (waits for the stream). count = nvar * nodes. */
+int dg_get_state(dg_solver *h, double *u, int64_t count);
+
+/* As dg_get_state into a device array of count doubles (stream-ordered). */
+int dg_get_state_device(dg_solver *h, void *u_dev, int64_t count);
+
+/* L2 error of the current state against a host reference u_ref (canonical
+ * layout, count = nvar * nodes), over all variables (Sec. 3.1 L2 norm, nodal
+ * LGL quadrature with the element Jacobian):
+ *   abs_err = sqrt(sum_v integral (U_v - Uref_v)^2),
+ *   rel_err = abs_err / sqrt(sum_v integral Uref_v^2)
+ * (rel_err = inf when the reference is zero). FP64 accumulation; waits for
+ * the stream. Either output pointer may be NULL. */
+int dg_l2_error(dg_solver *h, const double *u_ref, int64_t count, double *abs_err,
+                double *rel_err);
+
+/* Per-variable squared L2 norms: sq_err[v] = integral (U_v - Uref_v)^2 and
+ * sq_ref[v] = integral Uref_v^2 (arrays of nvar doubles). */
+int dg_l2_error_vars(dg_solver *h, const double *u_ref, int64_t count, double *sq_err,
+                     double *sq_ref);
+
+/* mass[v] = integral of U_v over the domain (nvar doubles), FP64; waits. */
+int dg_mass(dg_solver *h, double *mass);
+
+/* Wait for all work enqueued on the solver's stream. */
+int dg_synchronize(dg_solver *h);
+
+/* The solver's hipStream_t (as void*), for stream-ordered interop. */
+void *dg_stream(const dg_solver *h);
+
+/* Message for the calling thread's last non-OK return ("" if none). */
+const char *dg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DG_H */

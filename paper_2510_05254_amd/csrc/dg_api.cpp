@@ -1,0 +1,682 @@
+// dg_api.cpp -- host runtime behind the C ABI of include/dg.h: argument
+// validation, workspace carve-up, operator tables, the Runge-Kutta stage
+// schedules and the launch loop, reductions and host/device copies.
+//
+// Stage schedules (Sec. 2.3). Every scheme below is algebraically the
+// Butcher-form scheme of the paper; they differ only in which combinations of
+// stage vectors are kept in memory, chosen to minimise HBM passes.
+//
+// RK4 (eq. RK4), arrays U, A (accumulator), Ya, Yb, 14 array passes per step:
+//   s1: R1 = F(U);   Yb = U + dt/2 R1
+//   s2: R2 = F(Yb);  A  = U + (Yb - U)/3 + dt/3 R2  (= U + dt/6 R1 + dt/3 R2)
+//                    Ya = U + dt/2 R2
+//   s3: R3 = F(Ya);  A += dt/3 R3;  Yb = U + dt R3
+//   s4: R4 = F(Yb);  U  = A + dt/6 R4
+// RK3 (eq. RK3, Heun reading), 9 passes per step:
+//   s1: R1 = F(U);   Ya = U + dt/3 R1;  A = U + dt/4 R1
+//   s2: R2 = F(Ya);  Yb = U + 2dt/3 R2
+//   s3: R3 = F(Yb);  U  = A + 3dt/4 R3
+// RK6 (eq. RK6, Luther): k_s = dt F(Y_s) stored for s = 1..7, each followed
+//   by Y_{s+1} = U + (sum_j num_{s+1,j} k_j)/den_{s+1}, and finally
+//   U = U + (9k1 + 64k3 + 49k5 + 49k6 + 9k7)/180.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/dg.h"
+#include "dg_host.hpp"
+
+using namespace dg;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+constexpr size_t kAlign = 256;
+constexpr int64_t kReduceBlocks = 1024;
+
+size_t round_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    size_t tables = 0;      // D (real), w (double), reduction partials
+    size_t array = 0;       // one state array
+    size_t base = 0;        // tables + 4 arrays (RK3/RK4)
+    size_t rk6 = 0;         // base + 5 more arrays (RK6 k-store)
+};
+
+Layout layout_for(int dim, int N, const int64_t *K, int eq, int prec)
+{
+    Layout L;
+    int64_t nodes = 1;
+    for (int d = 0; d < dim; ++d) nodes *= K[d];
+    for (int d = 0; d < dim; ++d) nodes *= (N + 1);
+    const int nvar = eq == DG_ADVECTION ? 1 : 1 + dim;
+    const size_t sz = prec == DG_FP64 ? 8 : 4;
+    L.tables = round_up(sizeof(double) * kMaxNP1 * kMaxNP1) + round_up(sizeof(double) * kMaxNP1) +
+               round_up(sizeof(double) * 8 * kReduceBlocks);
+    L.array = round_up(sz * (size_t)nvar * (size_t)nodes);
+    L.base = L.tables + 4 * L.array;
+    L.rk6 = L.base + 5 * L.array;
+    return L;
+}
+
+int validate(int dim, int N, const int64_t *K, int eq, const double *params, int prec)
+{
+    if (dim < 1 || dim > 3) return fail(DG_EINVAL, "dim must be 1, 2 or 3");
+    if (N < 1 || N > kMaxN) return fail(DG_EINVAL, "N must be in 1..8");
+    if (!K) return fail(DG_EINVAL, "K is NULL");
+    double total = 1.0;
+    for (int d = 0; d < dim; ++d) {
+        if (K[d] < 1) return fail(DG_EINVAL, "K[d] must be >= 1");
+        total *= (double)K[d];
+    }
+    if (total * std::pow(N + 1.0, dim) * (1 + dim) > 9.0e18 / 8)
+        return fail(DG_EINVAL, "mesh too large");
+    if (eq != DG_ADVECTION && eq != DG_EULER_ISOTHERMAL)
+        return fail(DG_EINVAL, "equation must be DG_ADVECTION or DG_EULER_ISOTHERMAL");
+    if (!params) return fail(DG_EINVAL, "params is NULL");
+    if (eq == DG_ADVECTION) {
+        for (int d = 0; d < dim; ++d)
+            if (!std::isfinite(params[d])) return fail(DG_EINVAL, "advection velocity must be finite");
+    } else if (!std::isfinite(params[0]) || !(params[0] > 0.0)) {
+        return fail(DG_EINVAL, "sound speed c_s must be finite and > 0");
+    }
+    if (prec != DG_FP64 && prec != DG_FP32) return fail(DG_EINVAL, "precision must be DG_FP64 or DG_FP32");
+    return DG_OK;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(DG_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define DG_HIP(call, what)                          \
+    do {                                            \
+        hipError_t e_ = (call);                     \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+}  // namespace
+
+struct dg_solver {
+    int dim = 0, N = 0, eq = 0, prec = 0, nvar = 0, n1 = 0, np = 0;
+    int64_t K[3] = {1, 1, 1};
+    int64_t nodes = 0, unknowns = 0;
+    double par[3] = {0, 0, 0};
+    double xi[kMaxNP1], w[kMaxNP1], D[kMaxNP1 * kMaxNP1];
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    bool own_ws = false;
+    Layout lay;
+    void *Dtab = nullptr;
+    double *wtab = nullptr;
+    double *partial = nullptr;
+    void *U = nullptr, *A = nullptr, *Ya = nullptr, *Yb = nullptr;
+    void *kx[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // RK6 k3..k7
+    char *rk6_mem = nullptr;        // library-owned RK6 extension
+    bool has_state = false;
+    StageFn stage = nullptr;
+    int epb = 0;
+    int64_t tiles_x = 0, slab = 1, ntiles = 0, grid = 0;
+};
+
+namespace {
+
+int select_device(const dg_solver *h)
+{
+    DG_HIP(hipSetDevice(h->device), "hipSetDevice");
+    return DG_OK;
+}
+
+StageParams base_params(const dg_solver *h)
+{
+    StageParams p;
+    std::memset(&p, 0, sizeof(p));
+    for (int d = 0; d < 3; ++d) {
+        p.K[d] = h->K[d];
+        p.rdx2[d] = d < h->dim ? 2.0 * (double)h->K[d] : 0.0;
+        p.par[d] = h->par[d];
+    }
+    p.stride = h->nodes;
+    p.D = h->Dtab;
+    p.tiles_x = h->tiles_x;
+    p.slab = h->slab;
+    p.ntiles = h->ntiles;
+    return p;
+}
+
+// One fused stage: R = F(yin); out_o = cy yin + c0 in0 + c1 in1 + cr R.
+struct Out {
+    void *ptr;
+    double cy, c0, c1, cr;
+};
+
+int run_stage(dg_solver *h, const void *yin, const void *in0, const void *in1, int nin,
+              std::initializer_list<Out> outs)
+{
+    StageParams p = base_params(h);
+    p.yin = yin;
+    p.in0 = in0;
+    p.in1 = in1;
+    p.nin = nin;
+    int o = 0;
+    for (const Out &x : outs) {
+        (o == 0 ? p.out0 : p.out1) = x.ptr;
+        p.cy[o] = x.cy;
+        p.c0[o] = x.c0;
+        p.c1[o] = x.c1;
+        p.cr[o] = x.cr;
+        ++o;
+    }
+    p.nout = o;
+    DG_HIP(h->stage(p, h->grid, h->stream), "stage kernel launch");
+    return DG_OK;
+}
+
+int ensure_rk6(dg_solver *h)
+{
+    if (h->kx[0]) return DG_OK;
+    char *mem = nullptr;
+    if (!h->own_ws) {
+        if (h->ws_bytes < h->lay.rk6)
+            return fail(DG_ENOMEM, "workspace too small for RK6 (see dg_workspace_bytes)");
+        mem = h->ws + h->lay.base;
+    } else {
+        hipError_t e = hipMalloc((void **)&h->rk6_mem, 5 * h->lay.array);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            h->rk6_mem = nullptr;
+            return fail(DG_ENOMEM, "cannot allocate the RK6 stage store");
+        }
+        mem = h->rk6_mem;
+    }
+    for (int i = 0; i < 5; ++i) h->kx[i] = mem + i * h->lay.array;
+    return DG_OK;
+}
+
+int run_combine(dg_solver *h, void *out, const void *base, double a_base,
+                const std::vector<std::pair<const void *, double>> &src, double scale)
+{
+    CombineParams c;
+    std::memset(&c, 0, sizeof(c));
+    c.base = base;
+    c.a_base = a_base;
+    c.scale = scale;
+    c.nsrc = (int)src.size();
+    for (size_t j = 0; j < src.size(); ++j) {
+        c.src[j] = src[j].first;
+        c.c[j] = src[j].second;
+    }
+    c.out = out;
+    c.n = h->unknowns;
+    DG_HIP(launch_combine(h->prec, c, h->stream), "combine kernel launch");
+    return DG_OK;
+}
+
+int step_rk4(dg_solver *h, double dt)
+{
+    int rc;
+    if ((rc = run_stage(h, h->U, nullptr, nullptr, 0, {{h->Yb, 1.0, 0.0, 0.0, dt / 2}})))
+        return rc;
+    if ((rc = run_stage(h, h->Yb, h->U, nullptr, 1,
+                        {{h->A, 1.0 / 3.0, 2.0 / 3.0, 0.0, dt / 3}, {h->Ya, 0.0, 1.0, 0.0, dt / 2}})))
+        return rc;
+    if ((rc = run_stage(h, h->Ya, h->U, h->A, 2,
+                        {{h->A, 0.0, 0.0, 1.0, dt / 3}, {h->Yb, 0.0, 1.0, 0.0, dt}})))
+        return rc;
+    return run_stage(h, h->Yb, h->A, nullptr, 1, {{h->U, 0.0, 1.0, 0.0, dt / 6}});
+}
+
+int step_rk3(dg_solver *h, double dt)
+{
+    int rc;
+    if ((rc = run_stage(h, h->U, nullptr, nullptr, 0,
+                        {{h->Ya, 1.0, 0.0, 0.0, dt / 3}, {h->A, 1.0, 0.0, 0.0, dt / 4}})))
+        return rc;
+    if ((rc = run_stage(h, h->Ya, h->U, nullptr, 1, {{h->Yb, 0.0, 1.0, 0.0, 2.0 * dt / 3}})))
+        return rc;
+    return run_stage(h, h->Yb, h->A, nullptr, 1, {{h->U, 0.0, 1.0, 0.0, 3.0 * dt / 4}});
+}
+
+// Luther's RK6 (eq. RK6): Y_s = U + (sum_j num[s][j] k_j) / den[s].
+struct Rk6Tableau {
+    double num[7][7];
+    double den[7];
+    double bnum[7];
+    double bden;
+};
+
+const Rk6Tableau &rk6_tableau()
+{
+    static const Rk6Tableau t = [] {
+        Rk6Tableau r;
+        std::memset(&r, 0, sizeof(r));
+        const double q = std::sqrt(21.0);
+        r.den[1] = 1;    r.num[1][0] = 1;
+        r.den[2] = 8;    r.num[2][0] = 3; r.num[2][1] = 1;
+        r.den[3] = 27;   r.num[3][0] = 8; r.num[3][1] = 2; r.num[3][2] = 8;
+        r.den[4] = 392;
+        r.num[4][0] = 3 * (3 * q - 7);   r.num[4][1] = -8 * (7 - q);
+        r.num[4][2] = 48 * (7 - q);      r.num[4][3] = -3 * (21 - q);
+        r.den[5] = 1960;
+        r.num[5][0] = -5 * (231 + 51 * q); r.num[5][1] = -40 * (7 + q);
+        r.num[5][2] = -320 * q;            r.num[5][3] = 3 * (21 + 121 * q);
+        r.num[5][4] = 392 * (6 + q);
+        r.den[6] = 180;
+        r.num[6][0] = 15 * (22 + 7 * q);  r.num[6][1] = 120;
+        r.num[6][2] = 40 * (7 * q - 5);   r.num[6][3] = -63 * (3 * q - 2);
+        r.num[6][4] = -14 * (49 + 9 * q); r.num[6][5] = 70 * (7 - q);
+        r.bden = 180;
+        r.bnum[0] = 9; r.bnum[2] = 64; r.bnum[4] = 49; r.bnum[5] = 49; r.bnum[6] = 9;
+        return r;
+    }();
+    return t;
+}
+
+int step_rk6(dg_solver *h, double dt)
+{
+    const Rk6Tableau &t = rk6_tableau();
+    void *k[7] = {h->A, h->Yb, h->kx[0], h->kx[1], h->kx[2], h->kx[3], h->kx[4]};
+    void *Y = h->Ya;
+    int rc;
+    for (int s = 0; s < 7; ++s) {
+        const void *ys = s == 0 ? h->U : Y;
+        if ((rc = run_stage(h, ys, nullptr, nullptr, 0, {{k[s], 0.0, 0.0, 0.0, dt}}))) return rc;
+        std::vector<std::pair<const void *, double>> src;
+        if (s < 6) {
+            for (int j = 0; j <= s; ++j)
+                if (t.num[s + 1][j] != 0.0) src.push_back({k[j], t.num[s + 1][j]});
+            if ((rc = run_combine(h, Y, h->U, 1.0, src, 1.0 / t.den[s + 1]))) return rc;
+        } else {
+            for (int j = 0; j < 7; ++j)
+                if (t.bnum[j] != 0.0) src.push_back({k[j], t.bnum[j]});
+            if ((rc = run_combine(h, h->U, h->U, 1.0, src, 1.0 / t.bden))) return rc;
+        }
+    }
+    return DG_OK;
+}
+
+int check_count(const dg_solver *h, int64_t count)
+{
+    if (count != h->unknowns)
+        return fail(DG_EINVAL, "count must equal nvar * nodes = " + std::to_string(h->unknowns));
+    return DG_OK;
+}
+
+// Reduction over the current state (mode 0: mass; mode 1: L2 against the
+// FP64 reference already staged at uref_dev). Returns per-variable sums.
+int reduce(dg_solver *h, int mode, const double *uref_dev, double *s0, double *s1)
+{
+    ReduceParams r;
+    std::memset(&r, 0, sizeof(r));
+    r.u = h->U;
+    r.uref = uref_dev;
+    r.partial = h->partial;
+    r.w = h->wtab;
+    double jac = 1.0;
+    for (int d = 0; d < h->dim; ++d) jac *= 0.5 / (double)h->K[d];
+    r.jac = jac;
+    r.stride = h->nodes;
+    r.nvar = h->nvar;
+    r.n1 = h->n1;
+    r.np = h->np;
+    r.dim = h->dim;
+    r.mode = mode;
+    int64_t blocks = (h->nodes + kReduceThreads - 1) / kReduceThreads;
+    blocks = std::min<int64_t>(std::max<int64_t>(blocks, 1), kReduceBlocks);
+    DG_HIP(launch_reduce(h->prec, r, blocks, h->stream), "reduce kernel launch");
+    std::vector<double> part(8 * blocks);
+    DG_HIP(hipMemcpyAsync(part.data(), h->partial, sizeof(double) * 8 * blocks,
+                          hipMemcpyDeviceToHost, h->stream), "hipMemcpyAsync");
+    DG_HIP(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    for (int v = 0; v < h->nvar; ++v) {
+        double a = 0.0, b = 0.0;
+        for (int64_t i = 0; i < blocks; ++i) {
+            a += part[8 * i + v];
+            b += part[8 * i + 4 + v];
+        }
+        s0[v] = a;
+        if (s1) s1[v] = b;
+    }
+    return DG_OK;
+}
+
+// Stage an FP64 host reference on the device (in the Ya/Yb region, free
+// between steps: Ya and Yb are adjacent and together hold >= unknowns doubles).
+int stage_reference(dg_solver *h, const double *u_ref, double **dev)
+{
+    double *d = static_cast<double *>(h->Ya);
+    DG_HIP(hipMemcpyAsync(d, u_ref, sizeof(double) * h->unknowns, hipMemcpyHostToDevice, h->stream),
+           "hipMemcpyAsync");
+    *dev = d;
+    return DG_OK;
+}
+
+void free_solver(dg_solver *h)
+{
+    if (!h) return;
+    (void)hipSetDevice(h->device);
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    if (h->rk6_mem) (void)hipFree(h->rk6_mem);
+    if (h->own_ws && h->ws) (void)hipFree(h->ws);
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *dg_last_error(void) { return g_last_error.c_str(); }
+
+int dg_workspace_bytes(int dim, int N, const int64_t *K, int equation, int precision, int rk,
+                       size_t *bytes)
+{
+    double dummy[3] = {1.0, 1.0, 1.0};
+    int rc = validate(dim, N, K, equation, dummy, precision);
+    if (rc) return rc;
+    if (rk != DG_RK3 && rk != DG_RK4 && rk != DG_RK6) return fail(DG_EINVAL, "rk must be 3, 4 or 6");
+    if (!bytes) return fail(DG_EINVAL, "bytes is NULL");
+    Layout L = layout_for(dim, N, K, equation, precision);
+    *bytes = rk == DG_RK6 ? L.rk6 : L.base;
+    return DG_OK;
+}
+
+int dg_create_ex(int dim, int N, const int64_t *K, int equation, const double *params,
+                 int precision, void *hip_stream, void *device_workspace, size_t workspace_bytes,
+                 dg_solver **out)
+{
+    if (!out) return fail(DG_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate(dim, N, K, equation, params, precision);
+    if (rc) return rc;
+    StageFn fn = stage_fn(precision, equation, dim, N);
+    if (!fn) return fail(DG_ENOTSUP, "no stage kernel built for this configuration");
+
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        return fail(DG_EDEVICE, "no HIP device available");
+    }
+
+    dg_solver *h = new (std::nothrow) dg_solver();
+    if (!h) return fail(DG_ENOMEM, "host allocation failed");
+    h->dim = dim;
+    h->N = N;
+    h->eq = equation;
+    h->prec = precision;
+    h->nvar = equation == DG_ADVECTION ? 1 : 1 + dim;
+    h->n1 = N + 1;
+    h->np = 1;
+    for (int d = 0; d < dim; ++d) h->np *= h->n1;
+    int64_t E = 1;
+    for (int d = 0; d < 3; ++d) {
+        h->K[d] = d < dim ? K[d] : 1;
+        E *= h->K[d];
+    }
+    h->nodes = E * h->np;
+    h->unknowns = h->nodes * h->nvar;
+    if (equation == DG_ADVECTION)
+        for (int d = 0; d < dim; ++d) h->par[d] = params[d];
+    else
+        h->par[0] = params[0];
+    lgl_operator(N, h->xi, h->w, h->D);
+    h->lay = layout_for(dim, N, K, equation, precision);
+    h->stage = fn;
+    h->epb = stage_epb(dim, N);
+    h->tiles_x = (h->K[0] + h->epb - 1) / h->epb;
+    h->slab = 1;
+    if (dim == 3) {
+        for (int64_t s = std::max<int64_t>(1, h->K[2] / kXcds); s >= 1; --s)
+            if (h->K[2] % s == 0) { h->slab = s; break; }
+    }
+    h->ntiles = h->tiles_x * h->K[1] * h->K[2];
+    h->grid = std::min<int64_t>(h->ntiles, kMaxGrid);
+
+    e = hipGetDevice(&h->device);
+    if (e != hipSuccess) { delete h; return hip_fail(e, "hipGetDevice"); }
+
+    if (hip_stream) {
+        h->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+        e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) { delete h; return hip_fail(e, "hipStreamCreate"); }
+        h->own_stream = true;
+    }
+    if (device_workspace) {
+        if (workspace_bytes < h->lay.base) {
+            free_solver(h);
+            return fail(DG_ENOMEM, "workspace smaller than dg_workspace_bytes(rk=4)");
+        }
+        if ((reinterpret_cast<uintptr_t>(device_workspace) % kAlign) != 0) {
+            free_solver(h);
+            return fail(DG_EINVAL, "workspace must be 256-byte aligned");
+        }
+        h->ws = static_cast<char *>(device_workspace);
+        h->ws_bytes = workspace_bytes;
+    } else {
+        e = hipMalloc((void **)&h->ws, h->lay.base);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            h->ws = nullptr;
+            free_solver(h);
+            return fail(DG_ENOMEM, "cannot allocate " + std::to_string(h->lay.base) + " device bytes");
+        }
+        h->own_ws = true;
+        h->ws_bytes = h->lay.base;
+    }
+    char *p = h->ws;
+    h->Dtab = p;
+    p += round_up(sizeof(double) * kMaxNP1 * kMaxNP1);
+    h->wtab = reinterpret_cast<double *>(p);
+    p += round_up(sizeof(double) * kMaxNP1);
+    h->partial = reinterpret_cast<double *>(p);
+    p += round_up(sizeof(double) * 8 * kReduceBlocks);
+    h->U = p;  p += h->lay.array;
+    h->A = p;  p += h->lay.array;
+    h->Ya = p; p += h->lay.array;
+    h->Yb = p; p += h->lay.array;
+
+    // operator tables in the state precision (D) and FP64 (w)
+    unsigned char dbuf[sizeof(double) * kMaxNP1 * kMaxNP1];
+    const int nd = h->n1 * h->n1;
+    if (precision == DG_FP64) {
+        std::memcpy(dbuf, h->D, sizeof(double) * nd);
+    } else {
+        float *f = reinterpret_cast<float *>(dbuf);
+        for (int i = 0; i < nd; ++i) f[i] = (float)h->D[i];
+    }
+    const size_t dbytes = (precision == DG_FP64 ? 8 : 4) * (size_t)nd;
+    if ((e = hipMemcpyAsync(h->Dtab, dbuf, dbytes, hipMemcpyHostToDevice, h->stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(h->wtab, h->w, sizeof(double) * h->n1, hipMemcpyHostToDevice, h->stream)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(h->stream)) != hipSuccess) {
+        free_solver(h);
+        return hip_fail(e, "operator upload");
+    }
+    *out = h;
+    return DG_OK;
+}
+
+int dg_create(int dim, int N, const int64_t *K, int equation, const double *params, dg_solver **out)
+{
+    return dg_create_ex(dim, N, K, equation, params, DG_FP64, nullptr, nullptr, 0, out);
+}
+
+int dg_destroy(dg_solver *h)
+{
+    free_solver(h);
+    return DG_OK;
+}
+
+int dg_sizes(const dg_solver *h, int *nvar, int64_t *nodes)
+{
+    if (!h) return fail(DG_EINVAL, "solver is NULL");
+    if (nvar) *nvar = h->nvar;
+    if (nodes) *nodes = h->nodes;
+    return DG_OK;
+}
+
+int dg_get_axis_coords(const dg_solver *h, int axis, double *x, int64_t count)
+{
+    if (!h || !x) return fail(DG_EINVAL, "NULL argument");
+    if (axis < 0 || axis >= h->dim) return fail(DG_EINVAL, "axis out of range");
+    if (count != h->K[axis] * h->n1) return fail(DG_EINVAL, "count must be K[axis] * (N+1)");
+    const double dx = 1.0 / (double)h->K[axis];
+    for (int64_t e = 0; e < h->K[axis]; ++e)
+        for (int i = 0; i < h->n1; ++i) x[e * h->n1 + i] = (double)e * dx + 0.5 * dx * (h->xi[i] + 1.0);
+    return DG_OK;
+}
+
+int dg_set_state(dg_solver *h, const double *u, int64_t count)
+{
+    if (!h || !u) return fail(DG_EINVAL, "NULL argument");
+    int rc = check_count(h, count);
+    if (rc || (rc = select_device(h))) return rc;
+    if (h->prec == DG_FP64) {
+        DG_HIP(hipMemcpyAsync(h->U, u, sizeof(double) * count, hipMemcpyHostToDevice, h->stream),
+               "hipMemcpyAsync");
+    } else {
+        std::vector<float> tmp(count);
+        for (int64_t i = 0; i < count; ++i) tmp[i] = (float)u[i];
+        DG_HIP(hipMemcpyAsync(h->U, tmp.data(), sizeof(float) * count, hipMemcpyHostToDevice, h->stream),
+               "hipMemcpyAsync");
+        DG_HIP(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    }
+    DG_HIP(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    h->has_state = true;
+    return DG_OK;
+}
+
+int dg_set_state_device(dg_solver *h, const void *u_dev, int64_t count)
+{
+    if (!h || !u_dev) return fail(DG_EINVAL, "NULL argument");
+    int rc = check_count(h, count);
+    if (rc || (rc = select_device(h))) return rc;
+    if (h->prec == DG_FP64) {
+        DG_HIP(hipMemcpyAsync(h->U, u_dev, sizeof(double) * count, hipMemcpyDeviceToDevice, h->stream),
+               "hipMemcpyAsync");
+    } else {
+        CastParams c{u_dev, h->U, count};
+        DG_HIP(launch_cast(DG_FP32, DG_FP64, c, h->stream), "cast kernel launch");
+    }
+    h->has_state = true;
+    return DG_OK;
+}
+
+int dg_step(dg_solver *h, int rk, double dt, int64_t nsteps)
+{
+    if (!h) return fail(DG_EINVAL, "solver is NULL");
+    if (rk != DG_RK3 && rk != DG_RK4 && rk != DG_RK6) return fail(DG_EINVAL, "rk must be 3, 4 or 6");
+    if (!std::isfinite(dt) || !(dt > 0.0)) return fail(DG_EINVAL, "dt must be finite and > 0");
+    if (nsteps < 0) return fail(DG_EINVAL, "nsteps must be >= 0");
+    if (!h->has_state) return fail(DG_ESTATE, "dg_set_state has not been called");
+    if (nsteps == 0) return DG_OK;
+    int rc = select_device(h);
+    if (rc) return rc;
+    if (rk == DG_RK6 && (rc = ensure_rk6(h))) return rc;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        rc = rk == DG_RK4 ? step_rk4(h, dt) : rk == DG_RK3 ? step_rk3(h, dt) : step_rk6(h, dt);
+        if (rc) return rc;
+    }
+    return DG_OK;
+}
+
+int dg_get_state(dg_solver *h, double *u, int64_t count)
+{
+    if (!h || !u) return fail(DG_EINVAL, "NULL argument");
+    int rc = check_count(h, count);
+    if (rc || (rc = select_device(h))) return rc;
+    if (!h->has_state) return fail(DG_ESTATE, "dg_set_state has not been called");
+    if (h->prec == DG_FP64) {
+        DG_HIP(hipMemcpyAsync(u, h->U, sizeof(double) * count, hipMemcpyDeviceToHost, h->stream),
+               "hipMemcpyAsync");
+        DG_HIP(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    } else {
+        std::vector<float> tmp(count);
+        DG_HIP(hipMemcpyAsync(tmp.data(), h->U, sizeof(float) * count, hipMemcpyDeviceToHost, h->stream),
+               "hipMemcpyAsync");
+        DG_HIP(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+        for (int64_t i = 0; i < count; ++i) u[i] = (double)tmp[i];
+    }
+    return DG_OK;
+}
+
+int dg_get_state_device(dg_solver *h, void *u_dev, int64_t count)
+{
+    if (!h || !u_dev) return fail(DG_EINVAL, "NULL argument");
+    int rc = check_count(h, count);
+    if (rc || (rc = select_device(h))) return rc;
+    if (!h->has_state) return fail(DG_ESTATE, "dg_set_state has not been called");
+    if (h->prec == DG_FP64) {
+        DG_HIP(hipMemcpyAsync(u_dev, h->U, sizeof(double) * count, hipMemcpyDeviceToDevice, h->stream),
+               "hipMemcpyAsync");
+    } else {
+        CastParams c{h->U, u_dev, count};
+        DG_HIP(launch_cast(DG_FP64, DG_FP32, c, h->stream), "cast kernel launch");
+    }
+    return DG_OK;
+}
+
+int dg_l2_error_vars(dg_solver *h, const double *u_ref, int64_t count, double *sq_err, double *sq_ref)
+{
+    if (!h || !u_ref || !sq_err || !sq_ref) return fail(DG_EINVAL, "NULL argument");
+    int rc = check_count(h, count);
+    if (rc || (rc = select_device(h))) return rc;
+    if (!h->has_state) return fail(DG_ESTATE, "dg_set_state has not been called");
+    double *dref = nullptr;
+    if ((rc = stage_reference(h, u_ref, &dref))) return rc;
+    return reduce(h, 1, dref, sq_err, sq_ref);
+}
+
+int dg_l2_error(dg_solver *h, const double *u_ref, int64_t count, double *abs_err, double *rel_err)
+{
+    double se[4] = {0, 0, 0, 0}, sr[4] = {0, 0, 0, 0};
+    int rc = dg_l2_error_vars(h, u_ref, count, se, sr);
+    if (rc) return rc;
+    double a = 0.0, b = 0.0;
+    for (int v = 0; v < h->nvar; ++v) {
+        a += se[v];
+        b += sr[v];
+    }
+    a = std::sqrt(a);
+    if (abs_err) *abs_err = a;
+    if (rel_err) *rel_err = b > 0.0 ? a / std::sqrt(b) : HUGE_VAL;
+    return DG_OK;
+}
+
+int dg_mass(dg_solver *h, double *mass)
+{
+    if (!h || !mass) return fail(DG_EINVAL, "NULL argument");
+    int rc = select_device(h);
+    if (rc) return rc;
+    if (!h->has_state) return fail(DG_ESTATE, "dg_set_state has not been called");
+    return reduce(h, 0, nullptr, mass, nullptr);
+}
+
+int dg_synchronize(dg_solver *h)
+{
+    if (!h) return fail(DG_EINVAL, "solver is NULL");
+    int rc = select_device(h);
+    if (rc) return rc;
+    DG_HIP(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    return DG_OK;
+}
+
+void *dg_stream(const dg_solver *h) { return h ? static_cast<void *>(h->stream) : nullptr; }
+
+}  // extern "C"

@@ -1,0 +1,6 @@
+// Stage-kernel instantiations: float, 1-D, advection, N = 1..8.
+#include "dg_stage.hpp"
+
+namespace dg {
+StageFn stage_fn_f32_d1_adv(int N) { return pick_stage_n<float, 1, 0>(N); }
+}  // namespace dg

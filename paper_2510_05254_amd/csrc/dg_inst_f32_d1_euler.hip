@@ -1,0 +1,6 @@
+// Stage-kernel instantiations: float, 1-D, isothermal Euler, N = 1..8.
+#include "dg_stage.hpp"
+
+namespace dg {
+StageFn stage_fn_f32_d1_euler(int N) { return pick_stage_n<float, 1, 1>(N); }
+}  // namespace dg

@@ -1,0 +1,6 @@
+// Stage-kernel instantiations: float, 2-D, isothermal Euler, N = 1..8.
+#include "dg_stage.hpp"
+
+namespace dg {
+StageFn stage_fn_f32_d2_euler(int N) { return pick_stage_n<float, 2, 1>(N); }
+}  // namespace dg

@@ -1,0 +1,6 @@
+// Stage-kernel instantiations: double, 1-D, isothermal Euler, N = 1..8.
+#include "dg_stage.hpp"
+
+namespace dg {
+StageFn stage_fn_f64_d1_euler(int N) { return pick_stage_n<double, 1, 1>(N); }
+}  // namespace dg

@@ -1,0 +1,6 @@
+// Stage-kernel instantiations: double, 2-D, advection, N = 1..8.
+#include "dg_stage.hpp"
+
+namespace dg {
+StageFn stage_fn_f64_d2_adv(int N) { return pick_stage_n<double, 2, 0>(N); }
+}  // namespace dg

@@ -1,0 +1,90 @@
+// dg_internal.hpp -- types shared by the host runtime (dg_api.cpp) and the
+// gfx950 kernels. Not part of the public ABI (include/dg.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dg {
+
+constexpr int kMaxN = 8;
+constexpr int kMaxNP1 = kMaxN + 1;
+constexpr int kXcds = 8;                 // MI355X: 8 accelerator complex dies
+constexpr int64_t kMaxGrid = 1 << 20;    // launch cap; blocks loop beyond it
+
+// Parameters of one fused RHS + Runge-Kutta stage launch.
+//
+// The kernel evaluates R = RHS(yin) (the NDG right-hand side: volume term,
+// Lax-Friedrichs face flux and lift) and writes, for o < nout,
+//   out_o = cy[o] * yin + c0[o] * in0 + c1[o] * in1 + cr[o] * R
+// elementwise (terms with a zero count are skipped: in0 needs nin >= 1, in1
+// needs nin >= 2). out_o may alias in0/in1 (each node is read before it is
+// written, by the same thread) but never yin, which neighbouring elements
+// read during the launch.
+struct StageParams {
+    const void *yin;
+    const void *in0;
+    const void *in1;
+    void *out0;
+    void *out1;
+    double cy[2], c0[2], c1[2], cr[2];
+    int nin, nout;
+    int64_t K[3];          // elements per direction (1 for unused directions)
+    int64_t stride;        // nodes = prod(K) * Np (distance between variables)
+    double rdx2[3];        // 2 / dx_d = 2 K_d
+    double par[3];         // advection a_d, or {c_s} for isothermal Euler
+    const void *D;         // (N+1)^2 differentiation matrix, row-major, in the
+                           // state's precision: D[i*(N+1)+m] = h_m'(xi_i)
+    int64_t tiles_x;       // ceil(K[0] / elements-per-block)
+    int64_t slab;          // 3-D: z-layers per XCD slab (divides K[2])
+    int64_t ntiles;        // number of element tiles (virtual blocks)
+};
+
+// Elementwise linear combination (RK6 stage assembly):
+//   out = a_base * base + (sum_j c[j] * src[j]) * scale
+struct CombineParams {
+    const void *base;
+    const void *src[8];
+    double c[8];
+    double a_base;
+    double scale;
+    int nsrc;
+    void *out;
+    int64_t n;
+};
+
+// Quadrature reductions: per-block FP64 partial sums of
+//   mode 0 (mass): sum q_n U_v
+//   mode 1 (L2):   sum q_n (U_v - Uref_v)^2  and  sum q_n Uref_v^2
+// with q_n = prod_d (dx_d/2) w_{n_d}.
+struct ReduceParams {
+    const void *u;
+    const double *uref;
+    double *partial;       // [block][2*nvar]
+    const double *w;       // LGL weights, N+1
+    double jac;            // prod_d dx_d/2
+    int64_t stride;        // nodes
+    int nvar, n1, np, dim, mode;
+};
+
+// Precision conversion between the canonical FP64 layout and the state type.
+struct CastParams {
+    const void *src;
+    void *dst;
+    int64_t n;
+};
+
+typedef hipError_t (*StageFn)(const StageParams &p, int64_t grid, hipStream_t s);
+
+// Stage launcher for (precision, equation, dim, N); nullptr if not built.
+StageFn stage_fn(int precision, int equation, int dim, int N);
+// Threads per block and elements per block of the stage kernel for (dim, N).
+int stage_threads(int dim, int N);
+int stage_epb(int dim, int N);
+
+hipError_t launch_combine(int precision, const CombineParams &p, hipStream_t s);
+hipError_t launch_reduce(int precision, const ReduceParams &p, int64_t blocks, hipStream_t s);
+hipError_t launch_cast(int to_precision, int from_precision, const CastParams &p, hipStream_t s);
+constexpr int kReduceThreads = 256;
+
+}  // namespace dg

@@ -1,0 +1,168 @@
+// dg_misc.hip -- stage-kernel dispatch, the elementwise combination used to
+// assemble RK6 stages, FP64 quadrature reductions (mass, L2) and precision
+// casts between the canonical FP64 layout and the state type.
+#include "dg_stage.hpp"
+
+namespace dg {
+
+StageFn stage_fn_f64_d1_adv(int N);
+StageFn stage_fn_f64_d1_euler(int N);
+StageFn stage_fn_f64_d2_adv(int N);
+StageFn stage_fn_f64_d2_euler(int N);
+StageFn stage_fn_f64_d3_adv(int N);
+StageFn stage_fn_f64_d3_euler(int N);
+StageFn stage_fn_f32_d1_adv(int N);
+StageFn stage_fn_f32_d1_euler(int N);
+StageFn stage_fn_f32_d2_adv(int N);
+StageFn stage_fn_f32_d2_euler(int N);
+StageFn stage_fn_f32_d3_adv(int N);
+StageFn stage_fn_f32_d3_euler(int N);
+
+StageFn stage_fn(int precision, int equation, int dim, int N)
+{
+    typedef StageFn (*Pick)(int);
+    static const Pick table[2][3][2] = {
+        {{stage_fn_f64_d1_adv, stage_fn_f64_d1_euler},
+         {stage_fn_f64_d2_adv, stage_fn_f64_d2_euler},
+         {stage_fn_f64_d3_adv, stage_fn_f64_d3_euler}},
+        {{stage_fn_f32_d1_adv, stage_fn_f32_d1_euler},
+         {stage_fn_f32_d2_adv, stage_fn_f32_d2_euler},
+         {stage_fn_f32_d3_adv, stage_fn_f32_d3_euler}}};
+    if (precision < 0 || precision > 1 || equation < 0 || equation > 1 || dim < 1 || dim > 3)
+        return nullptr;
+    return table[precision][dim - 1][equation](N);
+}
+
+template <int DIM>
+static int threads_n(int N, bool epb)
+{
+    switch (N) {
+#define DG_CASE(n) \
+    case n: return epb ? Shape<DIM, n>::EPB : Shape<DIM, n>::THREADS;
+        DG_CASE(1) DG_CASE(2) DG_CASE(3) DG_CASE(4) DG_CASE(5) DG_CASE(6) DG_CASE(7) DG_CASE(8)
+#undef DG_CASE
+    default: return 0;
+    }
+}
+
+int stage_threads(int dim, int N)
+{
+    return dim == 1 ? threads_n<1>(N, false) : dim == 2 ? threads_n<2>(N, false) : threads_n<3>(N, false);
+}
+
+int stage_epb(int dim, int N)
+{
+    return dim == 1 ? threads_n<1>(N, true) : dim == 2 ? threads_n<2>(N, true) : threads_n<3>(N, true);
+}
+
+// ---------------------------------------------------------------------------
+// out = a_base * base + (sum_j c_j src_j) * scale   (RK6 stage assembly)
+// ---------------------------------------------------------------------------
+template <typename real>
+__global__ void __launch_bounds__(256) combine_kernel(const CombineParams p)
+{
+    const real *base = static_cast<const real *>(p.base);
+    real *out = static_cast<real *>(p.out);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < p.n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        real sum = real(0);
+        for (int j = 0; j < p.nsrc; ++j) sum += real(p.c[j]) * static_cast<const real *>(p.src[j])[i];
+        out[i] = real(p.a_base) * base[i] + sum * real(p.scale);
+    }
+}
+
+static int64_t grid_for(int64_t n, int threads)
+{
+    int64_t g = (n + threads - 1) / threads;
+    if (g > kMaxGrid) g = kMaxGrid;
+    return g < 1 ? 1 : g;
+}
+
+hipError_t launch_combine(int precision, const CombineParams &p, hipStream_t s)
+{
+    const int64_t g = grid_for(p.n, 256);
+    if (precision == 0)
+        hipLaunchKernelGGL(combine_kernel<double>, dim3((unsigned)g), dim3(256), 0, s, p);
+    else
+        hipLaunchKernelGGL(combine_kernel<float>, dim3((unsigned)g), dim3(256), 0, s, p);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// FP64 quadrature reductions: per-block partial sums (block tree in LDS); the
+// host adds the partials in block order, so results are deterministic.
+// ---------------------------------------------------------------------------
+template <typename real>
+__global__ void __launch_bounds__(kReduceThreads) reduce_kernel(const ReduceParams p)
+{
+    constexpr int T = kReduceThreads;
+    __shared__ double red[2 * 4][T];
+    const real *u = static_cast<const real *>(p.u);
+    double acc[2 * 4];
+    for (int k = 0; k < 2 * 4; ++k) acc[k] = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)T + threadIdx.x; i < p.stride;
+         i += (int64_t)gridDim.x * T) {
+        int n = int(i % p.np);
+        double q = p.jac;
+        for (int d = 0; d < p.dim; ++d) {
+            q *= p.w[n % p.n1];
+            n /= p.n1;
+        }
+        for (int v = 0; v < p.nvar; ++v) {
+            const double x = double(u[v * p.stride + i]);
+            if (p.mode == 0) {
+                acc[v] += q * x;
+            } else {
+                const double r = p.uref[v * p.stride + i];
+                const double df = x - r;
+                acc[v] += q * df * df;
+                acc[4 + v] += q * r * r;
+            }
+        }
+    }
+    for (int k = 0; k < 2 * 4; ++k) red[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int h = T / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            for (int k = 0; k < 2 * 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 2 * 4; ++k) p.partial[blockIdx.x * 8 + k] = red[k][0];
+}
+
+hipError_t launch_reduce(int precision, const ReduceParams &p, int64_t blocks, hipStream_t s)
+{
+    if (precision == 0)
+        hipLaunchKernelGGL(reduce_kernel<double>, dim3((unsigned)blocks), dim3(kReduceThreads), 0, s, p);
+    else
+        hipLaunchKernelGGL(reduce_kernel<float>, dim3((unsigned)blocks), dim3(kReduceThreads), 0, s, p);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// precision casts
+// ---------------------------------------------------------------------------
+template <typename To, typename From>
+__global__ void __launch_bounds__(256) cast_kernel(const CastParams p)
+{
+    const From *src = static_cast<const From *>(p.src);
+    To *dst = static_cast<To *>(p.dst);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < p.n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = To(src[i]);
+}
+
+hipError_t launch_cast(int to_precision, int from_precision, const CastParams &p, hipStream_t s)
+{
+    const int64_t g = grid_for(p.n, 256);
+    if (to_precision == 1 && from_precision == 0)
+        hipLaunchKernelGGL((cast_kernel<float, double>), dim3((unsigned)g), dim3(256), 0, s, p);
+    else if (to_precision == 0 && from_precision == 1)
+        hipLaunchKernelGGL((cast_kernel<double, float>), dim3((unsigned)g), dim3(256), 0, s, p);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+}  // namespace dg

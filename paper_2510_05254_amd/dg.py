@@ -1,0 +1,279 @@
+"""Thin ctypes binding of libdg (include/dg.h): argument marshalling only.
+
+Every function has the name of the C entry point it calls and raises
+``DgError`` on a non-OK status. Every step of the NDG path runs in the HIP
+kernels of libdg.so; there is no fallback: if the library is missing, loading
+raises ``ImportError``. Host arrays are numpy float64 in the canonical layout
+(nvar, nodes); device arrays may be torch tensors (float64, on the solver's
+device) or raw integer addresses.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdg.so")
+
+DG_OK, DG_EINVAL, DG_ENOMEM, DG_EDEVICE, DG_ENOTSUP, DG_ESTATE = 0, -1, -2, -3, -4, -5
+DG_ADVECTION, DG_EULER_ISOTHERMAL = 0, 1
+DG_RK3, DG_RK4, DG_RK6 = 3, 4, 6
+DG_FP64, DG_FP32 = 0, 1
+STATUS_NAMES = {0: "DG_OK", -1: "DG_EINVAL", -2: "DG_ENOMEM", -3: "DG_EDEVICE", -4: "DG_ENOTSUP",
+                -5: "DG_ESTATE"}
+
+# Every symbol include/dg.h declares, with (restype, argtypes).
+_P = ctypes.c_void_p
+_I, _I64, _D, _SZ = ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+SIGNATURES = {
+    "dg_create": (_I, [_I, _I, _P, _I, _P, _P]),
+    "dg_create_ex": (_I, [_I, _I, _P, _I, _P, _I, _P, _P, _SZ, _P]),
+    "dg_workspace_bytes": (_I, [_I, _I, _P, _I, _I, _I, _P]),
+    "dg_destroy": (_I, [_P]),
+    "dg_sizes": (_I, [_P, _P, _P]),
+    "dg_get_axis_coords": (_I, [_P, _I, _P, _I64]),
+    "dg_set_state": (_I, [_P, _P, _I64]),
+    "dg_set_state_device": (_I, [_P, _P, _I64]),
+    "dg_step": (_I, [_P, _I, _D, _I64]),
+    "dg_get_state": (_I, [_P, _P, _I64]),
+    "dg_get_state_device": (_I, [_P, _P, _I64]),
+    "dg_l2_error": (_I, [_P, _P, _I64, _P, _P]),
+    "dg_l2_error_vars": (_I, [_P, _P, _I64, _P, _P]),
+    "dg_mass": (_I, [_P, _P]),
+    "dg_synchronize": (_I, [_P]),
+    "dg_stream": (_P, [_P]),
+    "dg_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+class DgError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+def load():
+    """Load libdg.so (built in-tree by paper_2510_05254_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2510_05254_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _call(name, *args):
+    lib = load()
+    rc = getattr(lib, name)(*args)
+    if rc != DG_OK:
+        raise DgError(rc, name, lib.dg_last_error().decode())
+    return rc
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dev_ptr(x) -> ctypes.c_void_p:
+    if isinstance(x, int):
+        return ctypes.c_void_p(x)
+    if hasattr(x, "data_ptr"):
+        import torch
+        if x.dtype != torch.float64 or not x.is_cuda or not x.is_contiguous():
+            raise ValueError("device array must be a contiguous float64 tensor on the GPU")
+        return ctypes.c_void_p(x.data_ptr())
+    raise TypeError("expected a torch tensor or an integer device address")
+
+
+def _K(dim, K):
+    K = np.atleast_1d(np.asarray(K, dtype=np.int64))
+    if K.size == 1 and dim > 1:
+        K = np.repeat(K, dim)
+    return np.ascontiguousarray(K)
+
+
+def _params(params):
+    return np.ascontiguousarray(np.atleast_1d(np.asarray(params, dtype=np.float64)))
+
+
+def dg_workspace_bytes(dim, N, K, equation, precision=DG_FP64, rk=DG_RK4) -> int:
+    out = ctypes.c_size_t(0)
+    _call("dg_workspace_bytes", dim, N, _ptr(_K(dim, K)), equation, precision, rk, ctypes.byref(out))
+    return out.value
+
+
+def dg_create(dim, N, K, equation, params):
+    h = ctypes.c_void_p()
+    _call("dg_create", dim, N, _ptr(_K(dim, K)), equation, _ptr(_params(params)), ctypes.byref(h))
+    return h
+
+
+def dg_create_ex(dim, N, K, equation, params, precision=DG_FP64, hip_stream=None,
+                 device_workspace=None, workspace_bytes=0):
+    h = ctypes.c_void_p()
+    ws = None if device_workspace is None else _dev_ptr_any(device_workspace)
+    _call("dg_create_ex", dim, N, _ptr(_K(dim, K)), equation, _ptr(_params(params)), precision,
+          ctypes.c_void_p(hip_stream) if hip_stream else None, ws, int(workspace_bytes),
+          ctypes.byref(h))
+    return h
+
+
+def _dev_ptr_any(x):
+    if isinstance(x, int):
+        return ctypes.c_void_p(x)
+    return ctypes.c_void_p(x.data_ptr())
+
+
+def dg_destroy(h):
+    if h:
+        _call("dg_destroy", h)
+
+
+def dg_sizes(h):
+    nv, nodes = ctypes.c_int(0), ctypes.c_int64(0)
+    _call("dg_sizes", h, ctypes.byref(nv), ctypes.byref(nodes))
+    return nv.value, nodes.value
+
+
+def dg_get_axis_coords(h, axis, K_axis, N):
+    x = np.zeros((int(K_axis), N + 1))
+    _call("dg_get_axis_coords", h, axis, _ptr(x), x.size)
+    return x
+
+
+def dg_set_state(h, u):
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    _call("dg_set_state", h, _ptr(u), u.size)
+
+
+def dg_set_state_device(h, u_dev, count=None):
+    count = u_dev.numel() if count is None else count
+    _call("dg_set_state_device", h, _dev_ptr(u_dev), int(count))
+
+
+def dg_step(h, rk, dt, nsteps):
+    _call("dg_step", h, int(rk), float(dt), int(nsteps))
+
+
+def dg_get_state(h):
+    nv, nodes = dg_sizes(h)
+    u = np.empty((nv, nodes))
+    _call("dg_get_state", h, _ptr(u), u.size)
+    return u
+
+
+def dg_get_state_device(h, u_dev, count=None):
+    count = u_dev.numel() if count is None else count
+    _call("dg_get_state_device", h, _dev_ptr(u_dev), int(count))
+
+
+def dg_l2_error(h, u_ref):
+    u_ref = np.ascontiguousarray(u_ref, dtype=np.float64)
+    a, r = ctypes.c_double(0), ctypes.c_double(0)
+    _call("dg_l2_error", h, _ptr(u_ref), u_ref.size, ctypes.byref(a), ctypes.byref(r))
+    return a.value, r.value
+
+
+def dg_l2_error_vars(h, u_ref):
+    u_ref = np.ascontiguousarray(u_ref, dtype=np.float64)
+    nv, _ = dg_sizes(h)
+    se, sr = np.zeros(nv), np.zeros(nv)
+    _call("dg_l2_error_vars", h, _ptr(u_ref), u_ref.size, _ptr(se), _ptr(sr))
+    return se, sr
+
+
+def dg_mass(h):
+    nv, _ = dg_sizes(h)
+    m = np.zeros(nv)
+    _call("dg_mass", h, _ptr(m))
+    return m
+
+
+def dg_synchronize(h):
+    _call("dg_synchronize", h)
+
+
+def dg_stream(h) -> int:
+    return load().dg_stream(h) or 0
+
+
+def dg_last_error() -> str:
+    return load().dg_last_error().decode()
+
+
+class Solver:
+    """Owning wrapper around a dg_solver handle."""
+
+    def __init__(self, dim, N, K, equation, params, precision=DG_FP64, hip_stream=None,
+                 device_workspace=None, workspace_bytes=0):
+        self.dim, self.N = int(dim), int(N)
+        self.K = tuple(int(k) for k in _K(dim, K))
+        self.equation, self.precision = int(equation), int(precision)
+        self._ws = device_workspace       # keep an external workspace alive
+        if precision == DG_FP64 and hip_stream is None and device_workspace is None:
+            self.h = dg_create(dim, N, K, equation, params)
+        else:
+            self.h = dg_create_ex(dim, N, K, equation, params, precision, hip_stream,
+                                  device_workspace, workspace_bytes)
+        self.nvar, self.nodes = dg_sizes(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            dg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def axis_coords(self):
+        return [dg_get_axis_coords(self.h, d, self.K[d], self.N) for d in range(self.dim)]
+
+    def set_state(self, u):
+        dg_set_state(self.h, u)
+
+    def set_state_device(self, u_dev):
+        dg_set_state_device(self.h, u_dev)
+
+    def step(self, rk, dt, nsteps):
+        dg_step(self.h, rk, dt, nsteps)
+
+    def get_state(self):
+        return dg_get_state(self.h)
+
+    def get_state_device(self, u_dev):
+        dg_get_state_device(self.h, u_dev)
+
+    def l2_error(self, u_ref):
+        return dg_l2_error(self.h, u_ref)
+
+    def l2_error_vars(self, u_ref):
+        return dg_l2_error_vars(self.h, u_ref)
+
+    def mass(self):
+        return dg_mass(self.h)
+
+    def synchronize(self):
+        dg_synchronize(self.h)
+
+    @property
+    def stream(self) -> int:
+        return dg_stream(self.h)

@@ -209,7 +209,35 @@ def initial_state(w: Workload, axes) -> np.ndarray:
         return fourier_sum(axes, kv, ph, A)
     if w.ic in ("euler2d", "euler3d"):
         return _euler_ic(w, axes, rng)
+    if w.ic == "euler_random":
+        return _euler_random(w, axes, rng)
     raise ValueError(f"unknown initial condition {w.ic}")
+
+
+def _euler_random(w: Workload, axes, rng: SplitMix64) -> np.ndarray:
+    """Any dimension: rho = 1 + noise * delta (max |delta| = 1) and each velocity
+    component a sum of random modes, scaled to max speed mach * c_s."""
+    dim, a = w.dim, w.ic_args
+    M, kmax = int(a.get("modes", 4)), int(a.get("kmax", 2))
+    cs = float(w.params[0])
+
+    def modes(ncomp):
+        kv, ph, C = [], [], []
+        for _ in range(M):
+            kv.append(_draw_k(rng, dim, kmax))
+            ph.append(rng.uniform())
+            C.append([rng.uniform() for _ in range(ncomp)])
+        return fourier_sum(axes, kv, ph, np.array(C))
+
+    delta = modes(1)[0]
+    delta /= np.abs(delta).max()
+    rho = 1.0 + float(a.get("noise", 0.2)) * delta
+    vel = modes(dim)
+    vel *= float(a.get("mach", 0.3)) * cs / np.sqrt((vel ** 2).sum(axis=0)).max()
+    U = np.empty((1 + dim, w.nodes))
+    U[0] = rho
+    U[1:] = rho[None, :] * vel
+    return U
 
 
 def _euler_ic(w: Workload, axes, rng: SplitMix64) -> np.ndarray:

@@ -1,0 +1,102 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point
+include/dg.h declares, and validates arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2510_05254_amd import dg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dg.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dg_[a-z0-9_]+)\s*\(", text)))
+
+
+def _has_gpu():
+    try:
+        import torch
+        return torch.cuda.device_count() > 0
+    except Exception:
+        return False
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ("dg_create", "dg_set_state", "dg_step", "dg_get_state", "dg_l2_error"):
+        assert must in names
+    assert set(names) == set(dg.SIGNATURES), set(names) ^ set(dg.SIGNATURES)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = dg.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    # the .so is a shared library built for gfx950 (the offload bundle names the target)
+    blob = open(dg.LIB_PATH, "rb").read()
+    assert b"gfx950" in blob
+
+
+@pytest.mark.parametrize("args,why", [
+    ((0, 3, [4], 0, [1.0]), "dim"),
+    ((4, 3, [4], 0, [1.0]), "dim"),
+    ((1, 0, [4], 0, [1.0]), "N"),
+    ((1, 9, [4], 0, [1.0]), "N"),
+    ((2, 3, [4, 0], 0, [1.0, 1.0]), "K"),
+    ((1, 3, [4], 2, [1.0]), "equation"),
+    ((1, 3, [4], 1, [0.0]), "sound speed"),
+    ((1, 3, [4], 1, [-1.0]), "sound speed"),
+    ((2, 3, [4, 4], 0, [1.0, float("nan")]), "velocity"),
+    ((1, 3, [4], 1, [float("inf")]), "sound speed"),
+])
+def test_create_rejects_invalid_arguments(args, why):
+    with pytest.raises(dg.DgError) as e:
+        dg.dg_create(*args)
+    assert e.value.status == dg.DG_EINVAL
+    assert why.split()[0].lower() in str(e.value).lower() or why in str(e.value)
+
+
+def test_create_rejects_bad_precision_and_null_out():
+    lib = dg.load()
+    K = np.array([4], dtype=np.int64)
+    p = np.array([1.0])
+    h = ctypes.c_void_p()
+    rc = lib.dg_create_ex(1, 3, K.ctypes.data_as(ctypes.c_void_p), 0, p.ctypes.data_as(ctypes.c_void_p),
+                          7, None, None, 0, ctypes.byref(h))
+    assert rc == dg.DG_EINVAL
+    rc = lib.dg_create(1, 3, K.ctypes.data_as(ctypes.c_void_p), 0, p.ctypes.data_as(ctypes.c_void_p), None)
+    assert rc == dg.DG_EINVAL
+
+
+def test_null_handle_calls_fail_cleanly():
+    lib = dg.load()
+    assert lib.dg_step(None, 4, 0.1, 1) == dg.DG_EINVAL
+    assert lib.dg_sizes(None, None, None) == dg.DG_EINVAL
+    assert lib.dg_destroy(None) == dg.DG_OK
+    assert lib.dg_stream(None) is None
+    assert "NULL" in dg.dg_last_error() or dg.dg_last_error() == ""
+
+
+def test_workspace_bytes():
+    b4 = dg.dg_workspace_bytes(3, 4, [64, 64, 64], 1, dg.DG_FP64, 4)
+    b6 = dg.dg_workspace_bytes(3, 4, [64, 64, 64], 1, dg.DG_FP64, 6)
+    b4f = dg.dg_workspace_bytes(3, 4, [64, 64, 64], 1, dg.DG_FP32, 4)
+    arr = 131072000 * 8
+    assert 4 * arr <= b4 < 4 * arr + 2 ** 20
+    assert b6 - b4 == 5 * arr
+    assert 4 * arr // 2 <= b4f < b4
+    with pytest.raises(dg.DgError):
+        dg.dg_workspace_bytes(3, 4, [64, 64, 64], 1, dg.DG_FP64, 5)
+
+
+@pytest.mark.skipif(_has_gpu(), reason="checks the no-device path")
+def test_valid_create_without_gpu_reports_edevice():
+    with pytest.raises(dg.DgError) as e:
+        dg.dg_create(1, 3, [64], 0, [1.0])
+    assert e.value.status == dg.DG_EDEVICE

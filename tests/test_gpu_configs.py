@@ -1,0 +1,89 @@
+"""GPU parity at the benchmark configurations' full sizes, in the launch
+configuration bench.py times.
+
+* Config 1 (1-D advection, K=64, N=3, to t=1 in 2316 RK4 steps): every output
+  against the oracle, and both against the exact translated solution.
+* Configs 2-4 at full mesh size: every output against the oracle after a
+  reduced number of steps the oracle finishes in seconds (2-D advection 10,
+  2-D Euler 5, 3-D Euler 1 step); then the full step count on the GPU alone,
+  checked by properties that hold at any size: mass conservation and, for
+  advection, the exact translated solution.
+"""
+import functools
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2510_05254_amd import dg
+from paper_2510_05254_amd import workloads as W
+from _helpers import PARITY_RTOL, rel_l2_per_var
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@functools.lru_cache(maxsize=1)
+def _inputs(cid):
+    w = W.config(cid)
+    ax = [oracle.axis_coords(w.N, k) for k in w.K]
+    U0 = W.initial_state(w, ax)
+    dt, n = W.time_step(w, ax, U0)
+    return w, ax, U0, dt, n
+
+
+def test_config1_full_run():
+    w, ax, U0, dt, n = _inputs(1)
+    _say(f"config 1: {n} RK4 steps dt={dt}")
+    with dg.Solver(w.dim, w.N, w.K, w.eq, w.params) as s:
+        s.set_state(U0)
+        s.step(4, dt, n)
+        Ug = s.get_state()
+        gpu_err = s.l2_error(U0)
+    Uo = oracle.step(w.dim, w.N, w.K, w.eq, w.params, U0, 4, dt, n)
+    assert np.all(rel_l2_per_var(Ug, Uo) <= PARITY_RTOL)
+    # after one revolution both equal U_0 up to the discretisation error
+    o_abs, o_rel = oracle.l2_error(w.dim, w.N, w.K, w.eq, Uo, U0)
+    assert abs(gpu_err[0] - o_abs) <= 1e-10 * o_abs
+    assert 1e-8 < o_rel < 1e-4, o_rel
+
+
+@pytest.mark.parametrize("cid,steps", [(2, 10), (3, 5), (4, 1)])
+def test_config_full_size_parity(cid, steps):
+    w, ax, U0, dt, n = _inputs(cid)
+    _say(f"config {cid}: {w.unknowns} unknowns, {steps} RK4 steps on GPU")
+    with dg.Solver(w.dim, w.N, w.K, w.eq, w.params) as s:
+        s.set_state(U0)
+        s.step(4, dt, steps)
+        Ug = s.get_state()
+    _say(f"config {cid}: oracle ({oracle.get_threads()} threads)")
+    Uo = oracle.step(w.dim, w.N, w.K, w.eq, w.params, U0, 4, dt, steps)
+    err = rel_l2_per_var(Ug, Uo)
+    _say(f"config {cid}: rel L2 per var {err}")
+    assert np.all(err <= PARITY_RTOL), err
+
+
+@pytest.mark.parametrize("cid", [2, 3, 4])
+def test_config_full_run_properties(cid):
+    w, ax, U0, dt, n = _inputs(cid)
+    _say(f"config {cid}: full {n} RK4 steps on GPU")
+    with dg.Solver(w.dim, w.N, w.K, w.eq, w.params) as s:
+        s.set_state(U0)
+        m0 = s.mass()
+        s.step(4, dt, n)
+        m1 = s.mass()
+        Ug = s.get_state()
+        if w.eq == W.ADVECTION:
+            exact = W.translated_advection(w, ax, n * dt)
+            a, r = s.l2_error(exact)
+    assert np.all(np.isfinite(Ug))
+    scale = np.maximum(np.abs(U0).max(axis=1), 1.0)
+    assert np.all(np.abs(m1 - m0) <= 1e-12 * scale), (m0, m1)
+    if w.eq == W.ADVECTION:
+        _say(f"config {cid}: L2 vs exact {a} rel {r}")
+        assert r < 1e-8, r

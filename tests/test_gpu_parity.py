@@ -1,0 +1,194 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU FP64 oracle.
+
+Bar: FP64 relative L2 per variable <= 1e-12 after a few full RK steps, for
+every (equation, dimension, degree 1..8, RK scheme). Meshes have several
+workgroup tiles along x with a ragged last tile, K_y != K_z, and the special
+cases K_d = 1 (an element is its own periodic neighbour), K_x below the tile
+width (the periodic wrap stays inside one tile) and K_z split into XCD slabs.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2510_05254_amd import dg
+from _helpers import ADV, EUL, PARITY_RTOL, case, params, ragged_K, rel_l2_per_var
+
+pytestmark = pytest.mark.gpu
+
+ALL = [(dim, N, eq) for dim in (1, 2, 3) for N in range(1, 9) for eq in (ADV, EUL)]
+
+
+def _run_both(dim, N, K, eq, rk, nsteps, seed=1234):
+    w, ax, U0, dt = case(dim, N, K, eq, seed)
+    with dg.Solver(dim, N, K, eq, params(dim, eq)) as s:
+        s.set_state(U0)
+        s.step(rk, dt, nsteps)
+        Ug = s.get_state()
+    Uo = oracle.step(dim, N, K, eq, params(dim, eq), U0, rk, dt, nsteps)
+    return U0, Ug, Uo
+
+
+@pytest.mark.parametrize("dim,N,eq", ALL)
+def test_parity_rk4(dim, N, eq):
+    K = ragged_K(dim, N)
+    U0, Ug, Uo = _run_both(dim, N, K, eq, 4, 3)
+    err = rel_l2_per_var(Ug, Uo)
+    assert np.all(err <= PARITY_RTOL), err
+    assert rel_l2_per_var(Uo, U0).max() > 1e3 * PARITY_RTOL     # the state really moved
+
+
+@pytest.mark.parametrize("rk", [3, 6])
+@pytest.mark.parametrize("dim,N,eq", [(d, n, e) for d in (1, 2, 3) for n in (1, 4, 8) for e in (ADV, EUL)])
+def test_parity_rk3_rk6(dim, N, eq, rk):
+    K = ragged_K(dim, N)
+    U0, Ug, Uo = _run_both(dim, N, K, eq, rk, 2)
+    assert np.all(rel_l2_per_var(Ug, Uo) <= PARITY_RTOL)
+
+
+@pytest.mark.parametrize("dim,N,K,eq", [
+    (1, 3, (1,), ADV), (1, 3, (1,), EUL), (2, 2, (1, 1), EUL), (3, 2, (1, 1, 1), EUL),
+    (2, 3, (5, 1), ADV), (3, 3, (2, 1, 3), EUL),      # K_d = 1 in some directions
+    (1, 2, (7,), EUL), (2, 1, (10, 4), ADV),          # K_x < tile width: wrap inside a tile
+    (3, 1, (3, 2, 16), EUL), (3, 4, (2, 2, 24), ADV),  # K_z split into XCD slabs
+    (2, 7, (4, 9), EUL), (3, 5, (4, 1, 2), ADV),
+])
+def test_parity_special_meshes(dim, N, K, eq):
+    U0, Ug, Uo = _run_both(dim, N, K, eq, 4, 2)
+    assert np.all(rel_l2_per_var(Ug, Uo) <= PARITY_RTOL)
+
+
+@pytest.mark.parametrize("dim,N,eq", [(1, 5, EUL), (2, 3, EUL), (3, 4, EUL), (3, 2, ADV)])
+def test_conservation_and_determinism(dim, N, eq):
+    K = ragged_K(dim, N)
+    w, ax, U0, dt = case(dim, N, K, eq)
+    with dg.Solver(dim, N, K, eq, params(dim, eq)) as s:
+        s.set_state(U0)
+        m0 = s.mass()
+        np.testing.assert_allclose(m0, oracle.mass(dim, N, K, eq, U0), rtol=1e-13, atol=1e-15)
+        s.step(4, dt, 20)
+        m1 = s.mass()
+        U1 = s.get_state()
+        s.set_state(U0)
+        s.step(4, dt, 20)
+        U2 = s.get_state()
+    scale = np.abs(U0).reshape(U0.shape[0], -1).max(axis=1) * 1.0
+    assert np.all(np.abs(m1 - m0) <= 1e-14 * np.maximum(scale, 1.0)), (m0, m1)
+    np.testing.assert_array_equal(U1, U2)            # bitwise repeatable
+
+
+def test_checkpoint_split_is_bitwise():
+    dim, N, K, eq = 2, 4, (5, 3), EUL
+    w, ax, U0, dt = case(dim, N, K, eq)
+    with dg.Solver(dim, N, K, eq, params(dim, eq)) as s:
+        s.set_state(U0)
+        s.step(4, dt, 7)
+        Ua = s.get_state()
+        s.set_state(U0)
+        s.step(4, dt, 3)
+        mid = s.get_state()
+    with dg.Solver(dim, N, K, eq, params(dim, eq)) as s2:
+        s2.set_state(mid)
+        s2.step(4, dt, 4)
+        Ub = s2.get_state()
+    np.testing.assert_array_equal(Ua, Ub)
+
+
+def test_reductions_match_oracle():
+    dim, N, K, eq = 3, 3, (3, 2, 2), EUL
+    w, ax, U0, dt = case(dim, N, K, eq)
+    ref = U0 * (1.0 + 1e-3 * np.sin(np.arange(U0.size)).reshape(U0.shape))
+    with dg.Solver(dim, N, K, eq, params(dim, eq)) as s:
+        s.set_state(U0)
+        se, sr = s.l2_error_vars(ref)
+        a, r = s.l2_error(ref)
+        m = s.mass()
+    ose, osr = oracle.l2(dim, N, K, eq, U0, ref)
+    np.testing.assert_allclose(se, ose, rtol=1e-12)
+    np.testing.assert_allclose(sr, osr, rtol=1e-13)
+    oa, orr = oracle.l2_error(dim, N, K, eq, U0, ref)
+    assert abs(a - oa) <= 1e-12 * oa and abs(r - orr) <= 1e-12 * orr
+    np.testing.assert_allclose(m, oracle.mass(dim, N, K, eq, U0), rtol=1e-13, atol=1e-16)
+
+
+@pytest.mark.parametrize("dim,N,K", [(1, 8, (5,)), (2, 3, (4, 3)), (3, 4, (2, 3, 5))])
+def test_axis_coords_and_roundtrip(dim, N, K):
+    with dg.Solver(dim, N, K, EUL, (1.0,)) as s:
+        for d, x in enumerate(s.axis_coords()):
+            np.testing.assert_allclose(x, oracle.axis_coords(N, K[d]), rtol=0, atol=4.5e-16)
+        U = np.random.default_rng(1).standard_normal((s.nvar, s.nodes))
+        s.set_state(U)
+        np.testing.assert_array_equal(s.get_state(), U)
+        s.step(4, 1e-9, 0)                   # nsteps = 0 is a no-op
+        np.testing.assert_array_equal(s.get_state(), U)
+
+
+def test_error_paths_on_device():
+    with dg.Solver(2, 3, (4, 4), ADV, (1.0, 0.5)) as s:
+        with pytest.raises(dg.DgError) as e:
+            s.step(4, 0.01, 1)
+        assert e.value.status == dg.DG_ESTATE
+        with pytest.raises(dg.DgError) as e:
+            s.set_state(np.zeros(10))
+        assert e.value.status == dg.DG_EINVAL
+        s.set_state(np.zeros((1, s.nodes)))
+        for bad in ((5, 0.01, 1), (4, 0.0, 1), (4, float("nan"), 1), (4, 0.01, -1)):
+            with pytest.raises(dg.DgError) as e:
+                s.step(*bad)
+            assert e.value.status == dg.DG_EINVAL
+        U = s.get_state()
+        assert np.all(U == 0)
+
+
+def test_device_arrays_stream_and_workspace():
+    import torch
+    dim, N, K, eq = 3, 2, (4, 3, 2), EUL
+    w, ax, U0, dt = case(dim, N, K, eq)
+    nbytes = dg.dg_workspace_bytes(dim, N, K, eq, dg.DG_FP64, 6)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.Stream()
+    with dg.Solver(dim, N, K, eq, params(dim, eq), hip_stream=stream.cuda_stream,
+                   device_workspace=ws, workspace_bytes=nbytes) as s:
+        assert s.stream == stream.cuda_stream
+        u = torch.from_numpy(U0).to("cuda")
+        torch.cuda.synchronize()
+        s.set_state_device(u)
+        s.step(6, dt, 2)
+        out = torch.empty_like(u)
+        s.get_state_device(out)
+        s.synchronize()
+        Ug = out.cpu().numpy()
+    Uo = oracle.step(dim, N, K, eq, params(dim, eq), U0, 6, dt, 2)
+    assert np.all(rel_l2_per_var(Ug, Uo) <= PARITY_RTOL)
+
+
+def test_workspace_too_small_for_rk6():
+    import torch
+    dim, N, K, eq = 2, 2, (3, 3), ADV
+    nbytes = dg.dg_workspace_bytes(dim, N, K, eq, dg.DG_FP64, 4)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    with dg.Solver(dim, N, K, eq, params(dim, eq), device_workspace=ws, workspace_bytes=nbytes) as s:
+        s.set_state(np.ones((1, s.nodes)))
+        s.step(4, 0.01, 1)
+        with pytest.raises(dg.DgError) as e:
+            s.step(6, 0.01, 1)
+        assert e.value.status == dg.DG_ENOMEM
+    with pytest.raises(dg.DgError) as e:
+        dg.Solver(dim, N, K, eq, params(dim, eq), device_workspace=ws, workspace_bytes=nbytes // 2)
+    assert e.value.status == dg.DG_ENOMEM
+
+
+@pytest.mark.parametrize("dim,N,eq", [(1, 3, ADV), (2, 7, ADV), (2, 3, EUL), (3, 4, EUL), (3, 8, EUL)])
+def test_fp32_against_fp64_oracle(dim, N, eq):
+    """FP32 state/RHS path: error against the FP64 oracle after 3 RK4 steps."""
+    K = ragged_K(dim, N)
+    w, ax, U0, dt = case(dim, N, K, eq)
+    with dg.Solver(dim, N, K, eq, params(dim, eq), precision=dg.DG_FP32) as s:
+        s.set_state(U0)
+        s.step(4, dt, 3)
+        Ug = s.get_state()
+        m = s.mass()
+    Uo = oracle.step(dim, N, K, eq, params(dim, eq), U0, 4, dt, 3)
+    err = rel_l2_per_var(Ug, Uo)
+    print(f"fp32 dim={dim} N={N} eq={eq} rel L2 per var {err}")
+    assert np.all(err <= 2e-6), err
+    np.testing.assert_allclose(m, oracle.mass(dim, N, K, eq, Uo), rtol=1e-6, atol=1e-7)
