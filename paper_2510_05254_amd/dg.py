@@ -63,6 +63,14 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2510_05254_amd.build`")
+    # PyTorch ships its own HIP runtime with the same SONAME (libamdhip64.so.7)
+    # as the system one libdg.so links against. Loading torch first makes the
+    # dynamic linker bind libdg.so to the runtime torch already loaded, so the
+    # process holds one HIP runtime and device pointers/streams are shared.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
         f = getattr(lib, name)

@@ -100,3 +100,13 @@ def test_valid_create_without_gpu_reports_edevice():
     with pytest.raises(dg.DgError) as e:
         dg.dg_create(1, 3, [64], 0, [1.0])
     assert e.value.status == dg.DG_EDEVICE
+
+
+def test_single_hip_runtime_in_process():
+    """libdg.so must bind to the HIP runtime torch loads (same SONAME), never a second copy."""
+    dg.load()
+    import torch  # noqa: F401
+    maps = open("/proc/self/maps").read()
+    hip = set(re.findall(r"\S*libamdhip64\S*", maps))
+    hsa = set(re.findall(r"\S*libhsa-runtime64\S*", maps))
+    assert len(hip) == 1 and len(hsa) == 1, (hip, hsa)
