@@ -44,6 +44,7 @@ int fail(int code, const std::string &msg)
 
 constexpr size_t kAlign = 256;
 constexpr int64_t kReduceBlocks = 1024;
+constexpr size_t kFaceTableBytes = 16384;
 
 size_t round_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -63,7 +64,7 @@ Layout layout_for(int dim, int N, const int64_t *K, int eq, int prec)
     const int nvar = eq == DG_ADVECTION ? 1 : 1 + dim;
     const size_t sz = prec == DG_FP64 ? 8 : 4;
     L.tables = round_up(sizeof(double) * kMaxNP1 * kMaxNP1) + round_up(sizeof(double) * kMaxNP1) +
-               round_up(sizeof(double) * 8 * kReduceBlocks);
+               round_up(sizeof(double) * 8 * kReduceBlocks) + round_up(kFaceTableBytes);
     L.array = round_up(sz * (size_t)nvar * (size_t)nodes);
     L.base = L.tables + 4 * L.array;
     L.rk6 = L.base + 5 * L.array;
@@ -78,8 +79,10 @@ int validate(int dim, int N, const int64_t *K, int eq, const double *params, int
     double total = 1.0;
     for (int d = 0; d < dim; ++d) {
         if (K[d] < 1) return fail(DG_EINVAL, "K[d] must be >= 1");
+        if (K[d] > (int64_t(1) << 30)) return fail(DG_EINVAL, "K[d] must be <= 2^30");
         total *= (double)K[d];
     }
+    if (total > 4.0e9) return fail(DG_EINVAL, "at most 4e9 elements");
     if (total * std::pow(N + 1.0, dim) * (1 + dim) > 9.0e18 / 8)
         return fail(DG_EINVAL, "mesh too large");
     if (eq != DG_ADVECTION && eq != DG_EULER_ISOTHERMAL)
@@ -123,6 +126,7 @@ struct dg_solver {
     Layout lay;
     void *Dtab = nullptr;
     double *wtab = nullptr;
+    uint32_t *ftab = nullptr;
     double *partial = nullptr;
     void *U = nullptr, *A = nullptr, *Ya = nullptr, *Yb = nullptr;
     void *kx[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // RK6 k3..k7
@@ -155,6 +159,13 @@ StageParams base_params(const dg_solver *h)
     p.tiles_x = h->tiles_x;
     p.slab = h->slab;
     p.ntiles = h->ntiles;
+    p.ntiles32 = (uint32_t)h->ntiles;
+    p.xq = (uint32_t)(h->ntiles / kXcds);
+    p.xr = (uint32_t)(h->ntiles % kXcds);
+    p.fd_tx = make_fastdiv((uint32_t)h->tiles_x);
+    p.fd_slab = make_fastdiv((uint32_t)h->slab);
+    p.fd_k1 = make_fastdiv((uint32_t)h->K[1]);
+    p.ftab = h->ftab;
     return p;
 }
 
@@ -486,6 +497,8 @@ int dg_create_ex(int dim, int N, const int64_t *K, int equation, const double *p
     p += round_up(sizeof(double) * kMaxNP1);
     h->partial = reinterpret_cast<double *>(p);
     p += round_up(sizeof(double) * 8 * kReduceBlocks);
+    h->ftab = reinterpret_cast<uint32_t *>(p);
+    p += round_up(kFaceTableBytes);
     h->U = p;  p += h->lay.array;
     h->A = p;  p += h->lay.array;
     h->Ya = p; p += h->lay.array;
@@ -501,7 +514,15 @@ int dg_create_ex(int dim, int N, const int64_t *K, int equation, const double *p
         for (int i = 0; i < nd; ++i) f[i] = (float)h->D[i];
     }
     const size_t dbytes = (precision == DG_FP64 ? 8 : 4) * (size_t)nd;
+    std::vector<uint32_t> ftab(4 * (size_t)face_table_size(dim, N, h->epb));
+    build_face_table(dim, N, h->epb, ftab.data());
+    if (ftab.size() * 4 > kFaceTableBytes) {
+        free_solver(h);
+        return fail(DG_ENOTSUP, "face table larger than reserved");
+    }
     if ((e = hipMemcpyAsync(h->Dtab, dbuf, dbytes, hipMemcpyHostToDevice, h->stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(h->ftab, ftab.data(), ftab.size() * 4, hipMemcpyHostToDevice, h->stream)) !=
+            hipSuccess ||
         (e = hipMemcpyAsync(h->wtab, h->w, sizeof(double) * h->n1, hipMemcpyHostToDevice, h->stream)) !=
             hipSuccess ||
         (e = hipStreamSynchronize(h->stream)) != hipSuccess) {

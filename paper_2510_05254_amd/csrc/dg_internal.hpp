@@ -12,6 +12,28 @@ constexpr int kMaxNP1 = kMaxN + 1;
 constexpr int kXcds = 8;                 // MI355X: 8 accelerator complex dies
 constexpr int64_t kMaxGrid = 1 << 20;    // launch cap; blocks loop beyond it
 
+// Unsigned 32-bit division by an invariant divisor d as a multiply-high, add
+// and shift ("round-up" magic-number method, Granlund & Montgomery, PLDI 1994):
+//   n / d = (umulhi(n, mul) + n) >> shift  for all n < 2^32,
+// with shift = ceil(log2 d) and mul = floor(2^32 (2^shift - d) / d) + 1 (mod 2^32).
+struct FastDiv {
+    uint32_t div, mul, shift, pad;
+};
+
+inline FastDiv make_fastdiv(uint32_t d)
+{
+    uint32_t l = 0;
+    while ((uint64_t(1) << l) < d) ++l;
+    const uint64_t m = ((uint64_t(1) << 32) * ((uint64_t(1) << l) - d)) / d + 1;
+    return FastDiv{d, uint32_t(m), l, 0};
+}
+
+__device__ __forceinline__ uint32_t fast_div(uint32_t n, const FastDiv &f)
+{
+    const uint32_t hi = __umulhi(n, f.mul);
+    return uint32_t((uint64_t(hi) + n) >> f.shift);
+}
+
 // Parameters of one fused RHS + Runge-Kutta stage launch.
 //
 // The kernel evaluates R = RHS(yin) (the NDG right-hand side: volume term,
@@ -38,6 +60,12 @@ struct StageParams {
     int64_t tiles_x;       // ceil(K[0] / elements-per-block)
     int64_t slab;          // 3-D: z-layers per XCD slab (divides K[2])
     int64_t ntiles;        // number of element tiles (virtual blocks)
+    // 32-bit tile decoding: virtual block b runs on XCD b % 8; tiles are
+    // renumbered L = x * xq + min(x, xr) + b / 8 so each XCD owns a contiguous
+    // range, then L -> (x-tile, z in slab, y, slab) by the divisions below.
+    uint32_t ntiles32, xq, xr, pad0;
+    FastDiv fd_tx, fd_slab, fd_k1;
+    const uint32_t *ftab;  // face-point descriptors of a tile (dg_tables.cpp)
 };
 
 // Elementwise linear combination (RK6 stage assembly):

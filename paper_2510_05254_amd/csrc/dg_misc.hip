@@ -38,7 +38,7 @@ static int threads_n(int N, bool epb)
 {
     switch (N) {
 #define DG_CASE(n) \
-    case n: return epb ? Shape<DIM, n>::EPB : Shape<DIM, n>::THREADS;
+    case n: return epb ? Geo<DIM, n>::EPB : Geo<DIM, n>::THREADS;
         DG_CASE(1) DG_CASE(2) DG_CASE(3) DG_CASE(4) DG_CASE(5) DG_CASE(6) DG_CASE(7) DG_CASE(8)
 #undef DG_CASE
     default: return 0;

@@ -11,36 +11,55 @@
 //                          - delta_{l_d,N} (1/w_N) (Fhat_upper - F_d(U_l)) ]
 //
 // with F_d the physical flux (eqs. advection2d, eulerIso2d), Fhat the
-// Lax-Friedrichs flux of eq. LF from the (lower, upper) traces of each face,
-// periodic neighbours, and w_0 = w_N = 2/(N(N+1)). The RK stage update is
-// applied in the same pass (StageParams).
+// Lax-Friedrichs flux of eq. LF, alpha the larger of the two traces' wave
+// speeds, periodic neighbours, and w_0 = w_N = 2/(N(N+1)). The Runge-Kutta
+// stage update is applied in the same pass (StageParams).
 //
-// Work decomposition (MI355X-specific, not from the paper):
-//  - a workgroup takes a tile of EPB consecutive elements along x, one thread
-//    per node, variables in registers; the canonical layout u[v][e][n] makes
-//    each variable of a tile one contiguous, coalesced run;
-//  - the state of the tile and, for Euler, the symmetric momentum-flux tensor
-//    m_d u_k + delta_dk rho c^2 (dim(dim+1)/2 arrays instead of dim*nvar) are
-//    staged in LDS; the D contractions read them there, D itself sits in LDS;
-//  - face traces of x-neighbours inside the tile come from LDS, all other
-//    neighbour traces from global memory (L2-resident: see the tile order);
-//  - tiles are ordered so that each XCD (private L2) sweeps a compact region:
-//    virtual block b runs on XCD b % 8, and tile index L is remapped so XCD x
-//    owns a contiguous range of L; in 3-D the L order is x-tile fastest, then
-//    z inside a slab of `slab` layers, then y, then slab, which keeps the
-//    y- and z-neighbours of a tile within a short window of recent tiles.
+// Work decomposition (MI355X-specific, not from the paper). A workgroup owns
+// a tile of EPB consecutive elements along x (EPB * (N+1)^dim nodes, ~256
+// threads) and runs three phases separated by barriers:
+//  1. node-parallel: load the stage input (one thread per node, variables in
+//     registers), stage it in LDS together with 1/rho and the symmetric
+//     momentum-flux tensor m_a m_b / rho + delta_ab rho c^2;
+//  2. face-parallel: one thread per face point of the tile (a host-built
+//     descriptor table lists them). Faces inside the tile read both sides from
+//     LDS and are evaluated once; faces to neighbouring tiles read the other
+//     side from global memory (prefetched before the first barrier). The
+//     lift (2/dx)(1/w_0)(Fhat - F) of each in-tile side goes to LDS;
+//  3. node-parallel: volume term (D held in LDS), plus the lifts, plus the RK
+//     combination, stored with one coalesced store per variable and output.
+// Fluxes are evaluated through one set of functions with FMA contraction off
+// and a fixed reciprocal sequence, so a face shared by two tiles gets the same
+// Fhat bits on both sides and the scheme conserves to roundoff.
+//
+// Addressing: when every state array fits the 32-bit buffer range, loads and
+// stores are raw buffer instructions with one 32-bit offset per node (the
+// variable offset rides in the scalar offset); otherwise 64-bit pointers.
+//
+// Tile order: virtual block b runs on XCD b % 8 (private L2 per XCD); tiles
+// are renumbered so each XCD owns a contiguous range, in the order x-tile
+// fastest, then z inside a slab of `slab` layers, then y, then slab, which
+// keeps the y- and z-neighbours of a tile among recently visited tiles.
 #pragma once
 
 #include "dg_internal.hpp"
 
 namespace dg {
 
+constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+
 template <int DIM, int N>
-struct Shape {
+struct Geo {
     static constexpr int N1 = N + 1;
-    static constexpr int NP = DIM == 1 ? N1 : (DIM == 2 ? N1 * N1 : N1 * N1 * N1);
+    static constexpr int NP = ipow(N1, DIM);          // nodes per element
+    static constexpr int NF1 = ipow(N1, DIM - 1);     // nodes per face
     static constexpr int EPB = (256 / NP) < 1 ? 1 : (256 / NP);
-    static constexpr int THREADS = ((EPB * NP + 63) / 64) * 64;
+    static constexpr int TN = EPB * NP;
+    static constexpr int THREADS = ((TN + 63) / 64) * 64;
+    static constexpr int NFX = (EPB + 1) * NF1;       // x-face points of a tile
+    static constexpr int NFO = EPB * 2 * NF1;         // face points per other direction
+    static constexpr int NF = NFX + (DIM - 1) * NFO;
+    static constexpr int NL = DIM * EPB * 2 * NF1;    // lift slots per variable
 };
 
 template <int EQ, int DIM>
@@ -49,115 +68,157 @@ struct Vars {
     static constexpr int NSYM = EQ == 0 ? 0 : DIM * (DIM + 1) / 2;
 };
 
-// index of the symmetric pair (d, k) in the packed momentum-flux tensor
 __device__ __forceinline__ constexpr int sym_index(int d, int k, int dim)
 {
     const int a = d < k ? d : k, b = d < k ? k : d;
-    // row-major upper triangle: (0,0)..(0,dim-1),(1,1)..
     return a * dim - (a * (a - 1)) / 2 + (b - a);
 }
 
-// Physical flux along D of state U and its largest absolute eigenvalue.
-template <typename real, int EQ, int DIM, int D>
-__device__ __forceinline__ void flux_and_speed(const real *U, const real *par, real *F, real &lam)
+// 1/x: hardware reciprocal estimate refined by Newton-Raphson steps
+// e = 1 - x r, r <- r + r e, written with explicit FMAs.
+__device__ __forceinline__ double recip(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ float recip(float x)
+{
+    float r = __builtin_amdgcn_rcpf(x);
+    float e = __builtin_fmaf(-x, r, 1.0f);
+    return __builtin_fmaf(r, e, r);
+}
+
+// Momentum-flux tensor entry m_a (m_b / rho) + delta_ab rho c^2, canonical
+// order a <= b, contraction off: LDS copies and recomputations agree bitwise.
+template <typename real>
+__device__ __forceinline__ real sym_flux(real ma, real mb, real rho, real rinv, real c2, bool diag)
+{
+#pragma clang fp contract(off)
+    real f = ma * (mb * rinv);
+    if (diag) f = f + rho * c2;
+    return f;
+}
+
+// largest absolute eigenvalue of the isothermal Euler flux Jacobian along d
+template <typename real>
+__device__ __forceinline__ real wave_speed(real md, real rinv, real c)
+{
+#pragma clang fp contract(off)
+    return fabs(md * rinv) + c;
+}
+
+template <typename real>
+__device__ __forceinline__ real sel(int idx, real a0, real a1, real a2)
+{
+    return idx == 0 ? a0 : (idx == 1 ? a1 : a2);
+}
+
+// flux along a runtime direction d of a state U held in registers
+template <typename real, int DIM, int EQ>
+__device__ __forceinline__ void flux_rt(const real *U, int d, const real *par, real *F, real &lam)
 {
     if constexpr (EQ == 0) {
-        F[0] = par[D] * U[0];
-        lam = fabs(par[D]);
+#pragma clang fp contract(off)
+        const real a = sel(d, par[0], par[1], par[2]);
+        F[0] = a * U[0];
+        lam = fabs(a);
     } else {
         const real c = par[0];
-        const real rinv = real(1) / U[0];
-        F[0] = U[1 + D];
+        const real c2 = c * c;
+        const real rinv = recip(U[0]);
+        const real md = sel(d, U[1], U[DIM > 1 ? 2 : 1], U[DIM > 2 ? 3 : 1]);
+        F[0] = md;
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
-            real f = U[1 + D] * (U[1 + k] * rinv);
-            if (k == D) f += U[0] * (c * c);
-            F[1 + k] = f;
+            const real mk = U[1 + k];
+            const bool le = d <= k;
+            F[1 + k] = sym_flux(le ? md : mk, le ? mk : md, U[0], rinv, c2, d == k);
         }
-        lam = fabs(U[1 + D] * rinv) + c;
+        lam = wave_speed(md, rinv, c);
     }
 }
 
-// Lax-Friedrichs flux (eq. LF) from the lower trace UL and upper trace UR.
-// Both elements sharing a face call this with the same (UL, UR), so the two
-// sides get bitwise-identical Fhat and the scheme conserves to roundoff.
-template <typename real, int EQ, int DIM, int D>
-__device__ __forceinline__ void lf_flux(const real *UL, const real *UR, const real *par, real *Fh)
-{
-    constexpr int NV = Vars<EQ, DIM>::NV;
-    real FL[NV], FR[NV], aL, aR;
-    flux_and_speed<real, EQ, DIM, D>(UL, par, FL, aL);
-    flux_and_speed<real, EQ, DIM, D>(UR, par, FR, aR);
-    const real alpha = aL > aR ? aL : aR;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) Fh[v] = real(0.5) * ((FL[v] + FR[v]) - alpha * (UR[v] - UL[v]));
-}
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb)
-{
-    const int64_t x = b % kXcds, j = b / kXcds, q = nb / kXcds, r = nb % kXcds;
-    return x * q + (x < r ? x : r) + j;
-}
+// State-array access: raw buffer (32-bit offsets) or 64-bit pointer.
+template <typename real, bool BUF>
+struct Arr;
 
-template <int DIM>
-__device__ __forceinline__ void tile_coords(int64_t L, const StageParams &p, int64_t &tx,
-                                            int64_t &ey, int64_t &ez)
-{
-    if constexpr (DIM == 1) {
-        tx = L; ey = 0; ez = 0;
-    } else if constexpr (DIM == 2) {
-        tx = L % p.tiles_x; ey = L / p.tiles_x; ez = 0;
-    } else {
-        tx = L % p.tiles_x;
-        int64_t r = L / p.tiles_x;
-        const int64_t zs = r % p.slab;
-        r /= p.slab;
-        ey = r % p.K[1];
-        ez = (r / p.K[1]) * p.slab + zs;
+template <typename real>
+struct Arr<real, true> {
+    using idx_t = uint32_t;
+    __amdgpu_buffer_rsrc_t r;
+    uint32_t vbytes;   // bytes between variables
+    __device__ __forceinline__ Arr(const void *p, int64_t stride, int nvar)
+    {
+        vbytes = uint32_t(stride * (int64_t)sizeof(real));
+        r = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0,
+                                              (int)(uint32_t(nvar) * vbytes), 0x00020000);
     }
-}
+    __device__ __forceinline__ real ld(int v, idx_t node) const
+    {
+        if constexpr (sizeof(real) == 8)
+            return __builtin_bit_cast(real, __builtin_amdgcn_raw_buffer_load_b64(
+                                                r, node * (uint32_t)sizeof(real), v * vbytes, 0));
+        else
+            return __builtin_bit_cast(real, __builtin_amdgcn_raw_buffer_load_b32(
+                                                r, node * (uint32_t)sizeof(real), v * vbytes, 0));
+    }
+    __device__ __forceinline__ void st(int v, idx_t node, real x) const
+    {
+        if constexpr (sizeof(real) == 8)
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r,
+                                                  node * (uint32_t)sizeof(real), v * vbytes, 0);
+        else
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), r,
+                                                  node * (uint32_t)sizeof(real), v * vbytes, 0);
+    }
+};
 
-template <int DIM, int N, int D>
-__device__ __forceinline__ int node_with(const int *ijk, int val)
-{
-    constexpr int N1 = N + 1;
-    int q[3] = {ijk[0], ijk[1], ijk[2]};
-    q[D] = val;
-    if constexpr (DIM == 1) return q[0];
-    else if constexpr (DIM == 2) return q[0] + N1 * q[1];
-    else return q[0] + N1 * (q[1] + N1 * q[2]);
-}
+template <typename real>
+struct Arr<real, false> {
+    using idx_t = int64_t;
+    real *p;
+    int64_t stride;
+    __device__ __forceinline__ Arr(const void *ptr, int64_t s, int)
+        : p(static_cast<real *>(const_cast<void *>(ptr))), stride(s) {}
+    __device__ __forceinline__ real ld(int v, idx_t node) const { return p[v * stride + node]; }
+    __device__ __forceinline__ void st(int v, idx_t node, real x) const { p[v * stride + node] = x; }
+};
 
-template <typename real, int DIM, int N, int EQ>
-__global__ void __launch_bounds__((Shape<DIM, N>::THREADS))
+template <typename real, int DIM, int N, int EQ, bool BUF>
+__global__ void __launch_bounds__((Geo<DIM, N>::THREADS)) __attribute__((amdgpu_waves_per_eu(4)))
 stage_kernel(const StageParams p)
 {
-    using S = Shape<DIM, N>;
-    constexpr int N1 = S::N1, NP = S::NP, EPB = S::EPB, TN = EPB * NP;
+    using G = Geo<DIM, N>;
+    constexpr int N1 = G::N1, NP = G::NP, NF1 = G::NF1, EPB = G::EPB, TN = G::TN;
+    constexpr int THREADS = G::THREADS, NF = G::NF, NL = G::NL;
     constexpr int NV = Vars<EQ, DIM>::NV, NSYM = Vars<EQ, DIM>::NSYM;
-    constexpr real INVW0 = real(N * (N + 1)) / real(2);   // 1/w_0 = 1/w_N
+    constexpr real INVW0 = real(N * (N + 1)) / real(2);     // 1/w_0 = 1/w_N
+    using A = Arr<real, BUF>;
+    using idx_t = typename A::idx_t;
 
     __shared__ real sY[NV][TN];
-    __shared__ real sP[NSYM > 0 ? NSYM : 1][TN];
+    __shared__ real sP[NSYM > 0 ? NSYM : 1][EQ == 1 ? TN : 1];
+    __shared__ real sRi[EQ == 1 ? TN : 1];
+    __shared__ real sL[NV][NL];
     __shared__ real sD[N1 * N1];
 
-    const real *yin = static_cast<const real *>(p.yin);
-    const real *in0 = static_cast<const real *>(p.in0);
-    const real *in1 = static_cast<const real *>(p.in1);
-    real *out0 = static_cast<real *>(p.out0);
-    real *out1 = static_cast<real *>(p.out1);
-    const int64_t stride = p.stride;
-
-    real par[3];
+    const A yin(p.yin, p.stride, NV);
+    real par[3], rdx2[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) par[d] = real(p.par[d]);
-    real rdx2[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) rdx2[d] = real(p.rdx2[d]);
+    for (int d = 0; d < 3; ++d) {
+        par[d] = real(p.par[d]);
+        rdx2[d] = real(p.rdx2[d]);
+    }
+    const real c2 = par[0] * par[0];
+    const int64_t K0 = p.K[0], K1 = p.K[1], K2 = p.K[2];
 
     const int tid = threadIdx.x;
     if (tid < N1 * N1) sD[tid] = static_cast<const real *>(p.D)[tid];
-
     const int slot = tid / NP;
     const int n = tid - slot * NP;
     int ijk[3];
@@ -165,109 +226,178 @@ stage_kernel(const StageParams p)
     ijk[1] = DIM > 1 ? (n / N1) % N1 : 0;
     ijk[2] = DIM > 2 ? n / (N1 * N1) : 0;
 
-    for (int64_t vb = blockIdx.x; vb < p.ntiles; vb += gridDim.x) {
-        const int64_t L = xcd_remap(vb, p.ntiles);
-        int64_t tx, ey, ez;
-        tile_coords<DIM>(L, p, tx, ey, ez);
-        const int64_t ex = tx * EPB + slot;
-        const bool active = slot < EPB && ex < p.K[0];
-        const int64_t ec[3] = {ex, ey, ez};
-        const int64_t e = ex + p.K[0] * (ey + p.K[1] * ez);
-        const int64_t gi = e * NP + n;
+    // this thread's first face point (tile independent)
+    uint32_t fw0 = 0, fw1 = 0, fw2 = 0, fw3 = 0;
+    if (tid < NF) {
+        fw0 = p.ftab[4 * tid + 0];
+        fw1 = p.ftab[4 * tid + 1];
+        fw2 = p.ftab[4 * tid + 2];
+        fw3 = p.ftab[4 * tid + 3];
+    }
 
-        real y[NV], a0[NV], a1[NV];
-        // neighbour traces fetched from global memory: tr[d][v]
-        real tr[DIM][NV];
-        bool glob[DIM];
-        if (active) {
-#pragma unroll
-            for (int v = 0; v < NV; ++v) y[v] = yin[v * stride + gi];
-            if (p.nin > 0) {
-#pragma unroll
-                for (int v = 0; v < NV; ++v) a0[v] = in0[v * stride + gi];
+    for (uint32_t vb = blockIdx.x; vb < p.ntiles32; vb += gridDim.x) {
+        // ---- tile coordinates (XCD-contiguous numbering, magic divisions)
+        const uint32_t xb = vb & (kXcds - 1), jb = vb / kXcds;
+        const uint32_t L = xb * p.xq + (xb < p.xr ? xb : p.xr) + jb;
+        int64_t tx, ey, ez;
+        if constexpr (DIM == 1) {
+            tx = L; ey = 0; ez = 0;
+        } else if constexpr (DIM == 2) {
+            const uint32_t r1 = fast_div(L, p.fd_tx);
+            tx = L - r1 * p.fd_tx.div; ey = r1; ez = 0;
+        } else {
+            const uint32_t r1 = fast_div(L, p.fd_tx);
+            const uint32_t r2 = fast_div(r1, p.fd_slab);
+            const uint32_t r3 = fast_div(r2, p.fd_k1);
+            tx = L - r1 * p.fd_tx.div;
+            const uint32_t zs = r1 - r2 * p.fd_slab.div;
+            ey = r2 - r3 * p.fd_k1.div;
+            ez = int64_t(r3) * p.fd_slab.div + zs;
+        }
+        const int64_t ex0 = tx * EPB;
+        const int nact = (int)((K0 - ex0) < EPB ? (K0 - ex0) : EPB);
+        const int64_t ebase = K0 * (ey + K1 * ez);     // element index of (0, ey, ez)
+
+        // global element of the side of face point (w0, ps) that lies outside the tile
+        auto outside_elem = [&](uint32_t w0, uint32_t ps, bool lglob) -> int64_t {
+            const int d = int(w0 & 3u), kind = int((w0 >> 18) & 3u);
+            if (kind == 0) {
+                int64_t ex = lglob ? ex0 - 1 : ex0 + nact;
+                if (ex < 0) ex += K0;
+                if (ex >= K0) ex -= K0;
+                return ebase + ex;
             }
-            if (p.nin > 1) {
-#pragma unroll
-                for (int v = 0; v < NV; ++v) a1[v] = in1[v * stride + gi];
+            int64_t yy = ey, zz = ez;
+            const int step = kind == 2 ? 1 : -1;
+            if (d == 1) {
+                yy += step;
+                if (yy < 0) yy += K1;
+                if (yy >= K1) yy -= K1;
+            } else {
+                zz += step;
+                if (zz < 0) zz += K2;
+                if (zz >= K2) zz -= K2;
             }
+            return ex0 + int64_t(ps) + K0 * (yy + K1 * zz);
+        };
+        // does face point (w0, ps) exist in this tile, and which sides are outside it
+        auto face_sides = [&](uint32_t w0, uint32_t ps, bool &valid, bool &lglob, bool &rglob) {
+            const int kind = int((w0 >> 18) & 3u);
+            const uint32_t lsl = (w0 >> 2) & 0xffu, rsl = (w0 >> 10) & 0xffu;
+            valid = kind == 0 ? ps <= uint32_t(nact) : ps < uint32_t(nact);
+            lglob = lsl == 0;
+            rglob = kind == 0 ? ps == uint32_t(nact) : rsl == 0;
+        };
+
+        // ---- prefetch the outside state of this thread's first face point
+        real g[NV];
+        if (tid < NF) {
+            bool valid, lglob, rglob;
+            face_sides(fw0, fw2, valid, lglob, rglob);
+            if (valid && (lglob || rglob)) {
+                const int64_t en = outside_elem(fw0, fw2, lglob);
+                const uint32_t node = lglob ? (fw1 & 0xffffu) : (fw1 >> 16);
+                const idx_t gn = idx_t(en * NP + node);
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) {
-                const int id = ijk[d];
-                const bool lo = id == 0, hi = id == N;
-                glob[d] = false;
-                if (lo || hi) {
-                    int64_t c = ec[d] + (hi ? 1 : -1);
-                    if (c < 0) c += p.K[d];
-                    if (c >= p.K[d]) c -= p.K[d];
-                    bool in_tile = false;
-                    if (d == 0) in_tile = (c / EPB) == tx;
-                    if (!in_tile) {
-                        glob[d] = true;
-                        int64_t cc[3] = {ec[0], ec[1], ec[2]};
-                        cc[d] = c;
-                        const int64_t enb = cc[0] + p.K[0] * (cc[1] + p.K[1] * cc[2]);
-                        int nn;
-                        if (d == 0) nn = node_with<DIM, N, 0>(ijk, hi ? 0 : N);
-                        else if (d == 1) nn = node_with<DIM, N, (DIM > 1 ? 1 : 0)>(ijk, hi ? 0 : N);
-                        else nn = node_with<DIM, N, (DIM > 2 ? 2 : 0)>(ijk, hi ? 0 : N);
-                        const int64_t gn = enb * NP + nn;
-#pragma unroll
-                        for (int v = 0; v < NV; ++v) tr[d][v] = yin[v * stride + gn];
-                    }
-                }
+                for (int v = 0; v < NV; ++v) g[v] = yin.ld(v, gn);
             }
         }
 
-        // stage state and fluxes in LDS
+        // ---- phase 1: state, 1/rho and flux tensor into LDS
+        const bool active = slot < nact;
         const int ln = slot * NP + n;
-        real Fown[DIM][NV];
+        const idx_t gi = idx_t((ebase + ex0 + slot) * NP + n);
+        real y[NV];
         if (active) {
 #pragma unroll
+            for (int v = 0; v < NV; ++v) y[v] = yin.ld(v, gi);
+#pragma unroll
             for (int v = 0; v < NV; ++v) sY[v][ln] = y[v];
-            if constexpr (EQ == 0) {
+            if constexpr (EQ == 1) {
+                const real rinv = recip(y[0]);
+                sRi[ln] = rinv;
 #pragma unroll
-                for (int d = 0; d < DIM; ++d) Fown[d][0] = par[d] * y[0];
-            } else {
-                const real c = par[0];
-                const real rinv = real(1) / y[0];
-                const real pr = y[0] * (c * c);
-                real u[DIM];
+                for (int a = 0; a < DIM; ++a)
 #pragma unroll
-                for (int k = 0; k < DIM; ++k) u[k] = y[1 + k] * rinv;
-#pragma unroll
-                for (int d = 0; d < DIM; ++d) {
-                    Fown[d][0] = y[1 + d];
-#pragma unroll
-                    for (int k = 0; k < DIM; ++k) {
-                        real f = y[1 + d] * u[k];
-                        if (k == d) f += pr;
-                        Fown[d][1 + k] = f;
-                    }
-                }
-#pragma unroll
-                for (int d = 0; d < DIM; ++d)
-#pragma unroll
-                    for (int k = d; k < DIM; ++k) sP[sym_index(d, k, DIM)][ln] = Fown[d][1 + k];
+                    for (int b = a; b < DIM; ++b)
+                        sP[sym_index(a, b, DIM)][ln] = sym_flux(y[1 + a], y[1 + b], y[0], rinv, c2, a == b);
             }
         }
         __syncthreads();
 
+        // ---- phase 2: Lax-Friedrichs flux at the tile's face points, lifts to LDS
+        for (int f = tid; f < NF; f += THREADS) {
+            uint32_t w0 = fw0, w1 = fw1, w2 = fw2, w3 = fw3;
+            if (f >= THREADS) {
+                w0 = p.ftab[4 * f + 0];
+                w1 = p.ftab[4 * f + 1];
+                w2 = p.ftab[4 * f + 2];
+                w3 = p.ftab[4 * f + 3];
+            }
+            bool valid, lglob, rglob;
+            face_sides(w0, w2, valid, lglob, rglob);
+            if (!valid) continue;
+            const int d = int(w0 & 3u);
+            const int lslot = int((w0 >> 2) & 0xffu) - 1, rslot = int((w0 >> 10) & 0xffu) - 1;
+            const int lnode = int(w1 & 0xffffu), rnode = int(w1 >> 16);
+            if (f >= THREADS && (lglob || rglob)) {
+                const int64_t en = outside_elem(w0, w2, lglob);
+                const idx_t gn = idx_t(en * NP + (lglob ? lnode : rnode));
+#pragma unroll
+                for (int v = 0; v < NV; ++v) g[v] = yin.ld(v, gn);
+            }
+            real UL[NV], UR[NV], FL[NV], FR[NV], lamL, lamR;
+            auto side_state = [&](bool glob, int sl, int node, real *U, real *F, real &lam) {
+                if (!glob) {
+                    const int q = sl * NP + node;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) U[v] = sY[v][q];
+                    if constexpr (EQ == 0) {
+#pragma clang fp contract(off)
+                        const real a = sel(d, par[0], par[1], par[2]);
+                        F[0] = a * U[0];
+                        lam = fabs(a);
+                    } else {
+                        F[0] = sY[1 + d][q];
+#pragma unroll
+                        for (int k = 0; k < DIM; ++k) F[1 + k] = sP[sym_index(d, k, DIM)][q];
+                        lam = wave_speed(F[0], sRi[q], par[0]);
+                    }
+                } else {
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) U[v] = g[v];
+                    flux_rt<real, DIM, EQ>(U, d, par, F, lam);
+                }
+            };
+            side_state(lglob, lslot, lnode, UL, FL, lamL);
+            side_state(rglob, rslot, rnode, UR, FR, lamR);
+            const real alpha = lamL > lamR ? lamL : lamR;
+            const real s = sel(d, rdx2[0], rdx2[1], rdx2[2]) * INVW0;
+            const int liftL = int(w3 & 0xffffu), liftR = int(w3 >> 16);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const real fh = real(0.5) * ((FL[v] + FR[v]) - alpha * (UR[v] - UL[v]));
+                if (!lglob) sL[v][liftL] = -s * (fh - FL[v]);
+                if (!rglob) sL[v][liftR] = s * (fh - FR[v]);
+            }
+        }
+        __syncthreads();
+
+        // ---- phase 3: volume term + lifts, RK stage combination, store
         if (active) {
             real R[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) R[v] = real(0);
             const int base = slot * NP;
-
-            // volume term: -(2/dx_d) sum_m D_{l_d m} F_d(..m..)
 #pragma unroll
             for (int d = 0; d < DIM; ++d) {
                 const int id = ijk[d];
                 const int sd = d == 0 ? 1 : (d == 1 ? N1 : N1 * N1);
-                const int line0 = base + n - id * sd;   // node with l_d = 0 on this line
+                const int line0 = base + n - id * sd;
                 real acc[NV];
 #pragma unroll
                 for (int v = 0; v < NV; ++v) acc[v] = real(0);
-#pragma unroll
+#pragma unroll 1
                 for (int m = 0; m < N1; ++m) {
                     const real dm = sD[id * N1 + m];
                     const int q = line0 + m * sd;
@@ -285,57 +415,38 @@ stage_kernel(const StageParams p)
 #pragma unroll
                     for (int v = 0; v < NV; ++v) R[v] -= rdx2[d] * acc[v];
                 }
-            }
-
-            // face terms: Lax-Friedrichs flux and lift at l_d = 0 and l_d = N
+                if (id == 0 || id == N) {
+                    const int t = d == 0 ? (DIM > 1 ? ijk[1] + N1 * ijk[2] : 0)
+                                         : (d == 1 ? ijk[0] + N1 * ijk[2] : ijk[0] + N1 * ijk[1]);
+                    const int li = ((d * EPB + slot) * 2 + (id == N ? 1 : 0)) * NF1 + t;
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) {
-                const int id = ijk[d];
-                const bool lo = id == 0, hi = id == N;
-                if (lo || hi) {
-                    real unb[NV];
-                    if (glob[d]) {
-#pragma unroll
-                        for (int v = 0; v < NV; ++v) unb[v] = tr[d][v];
-                    } else {
-                        // x-neighbour inside this tile (d == 0 only)
-                        int64_t c = ex + (hi ? 1 : -1);
-                        if (c < 0) c += p.K[0];
-                        if (c >= p.K[0]) c -= p.K[0];
-                        const int nslot = int(c - tx * EPB);
-                        const int nn = node_with<DIM, N, 0>(ijk, hi ? 0 : N);
-#pragma unroll
-                        for (int v = 0; v < NV; ++v) unb[v] = sY[v][nslot * NP + nn];
-                    }
-                    real UL[NV], UR[NV], Fh[NV];
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) {
-                        UL[v] = lo ? unb[v] : y[v];
-                        UR[v] = lo ? y[v] : unb[v];
-                    }
-                    if (d == 0) lf_flux<real, EQ, DIM, 0>(UL, UR, par, Fh);
-                    else if (d == 1) lf_flux<real, EQ, DIM, (DIM > 1 ? 1 : 0)>(UL, UR, par, Fh);
-                    else lf_flux<real, EQ, DIM, (DIM > 2 ? 2 : 0)>(UL, UR, par, Fh);
-                    const real s = lo ? rdx2[d] * INVW0 : -rdx2[d] * INVW0;
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) R[v] += s * (Fh[v] - Fown[d][v]);
+                    for (int v = 0; v < NV; ++v) R[v] += sL[v][li];
                 }
             }
-
-            // Runge-Kutta stage combination
+            real a0[NV], a1[NV];
+            if (p.nin > 0) {
+                const A in0(p.in0, p.stride, NV);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) a0[v] = in0.ld(v, gi);
+            }
+            if (p.nin > 1) {
+                const A in1(p.in1, p.stride, NV);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) a1[v] = in1.ld(v, gi);
+            }
 #pragma unroll
             for (int o = 0; o < 2; ++o) {
                 if (o < p.nout) {
                     const real cy = real(p.cy[o]), c0 = real(p.c0[o]), c1 = real(p.c1[o]),
                                cr = real(p.cr[o]);
-                    real *out = o == 0 ? out0 : out1;
+                    const A out(o == 0 ? p.out0 : p.out1, p.stride, NV);
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
                         real val = cy * y[v];
                         if (p.nin > 0) val += c0 * a0[v];
                         if (p.nin > 1) val += c1 * a1[v];
                         val += cr * R[v];
-                        out[v * stride + gi] = val;
+                        out.st(v, gi, val);
                     }
                 }
             }
@@ -347,8 +458,13 @@ stage_kernel(const StageParams p)
 template <typename real, int DIM, int N, int EQ>
 hipError_t launch_stage(const StageParams &p, int64_t grid, hipStream_t s)
 {
-    hipLaunchKernelGGL((stage_kernel<real, DIM, N, EQ>), dim3((unsigned)grid),
-                       dim3(Shape<DIM, N>::THREADS), 0, s, p);
+    const int64_t bytes = p.stride * Vars<EQ, DIM>::NV * (int64_t)sizeof(real);
+    if (bytes < (int64_t(1) << 31))
+        hipLaunchKernelGGL((stage_kernel<real, DIM, N, EQ, true>), dim3((unsigned)grid),
+                           dim3(Geo<DIM, N>::THREADS), 0, s, p);
+    else
+        hipLaunchKernelGGL((stage_kernel<real, DIM, N, EQ, false>), dim3((unsigned)grid),
+                           dim3(Geo<DIM, N>::THREADS), 0, s, p);
     return hipGetLastError();
 }
 
