@@ -63,7 +63,8 @@ struct StageParams {
     // 32-bit tile decoding: virtual block b runs on XCD b % 8; tiles are
     // renumbered L = x * xq + min(x, xr) + b / 8 so each XCD owns a contiguous
     // range, then L -> (x-tile, z in slab, y, slab) by the divisions below.
-    uint32_t ntiles32, xq, xr, pad0;
+    uint32_t ntiles32, xq, xr;
+    uint32_t plain_order;  // 1: tile L = virtual block (no XCD renumbering)
     FastDiv fd_tx, fd_slab, fd_k1;
     const uint32_t *ftab;  // face-point descriptors of a tile (dg_tables.cpp)
 };

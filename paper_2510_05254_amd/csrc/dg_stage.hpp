@@ -42,18 +42,21 @@
 // keeps the y- and z-neighbours of a tile among recently visited tiles.
 #pragma once
 
+#include <type_traits>
+
 #include "dg_internal.hpp"
 
 namespace dg {
 
 constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 
-template <int DIM, int N>
+// TM scales the tile: EPB = max(1, 256 TM / (N+1)^dim) elements per workgroup
+template <int DIM, int N, int TM = 1>
 struct Geo {
     static constexpr int N1 = N + 1;
     static constexpr int NP = ipow(N1, DIM);          // nodes per element
     static constexpr int NF1 = ipow(N1, DIM - 1);     // nodes per face
-    static constexpr int EPB = (256 / NP) < 1 ? 1 : (256 / NP);
+    static constexpr int EPB = (256 * TM / NP) < 1 ? 1 : (256 * TM / NP);
     static constexpr int TN = EPB * NP;
     static constexpr int THREADS = ((TN + 63) / 64) * 64;
     static constexpr int NFX = (EPB + 1) * NF1;       // x-face points of a tile
@@ -110,34 +113,26 @@ __device__ __forceinline__ real wave_speed(real md, real rinv, real c)
     return fabs(md * rinv) + c;
 }
 
-template <typename real>
-__device__ __forceinline__ real sel(int idx, real a0, real a1, real a2)
-{
-    return idx == 0 ? a0 : (idx == 1 ? a1 : a2);
-}
-
-// flux along a runtime direction d of a state U held in registers
-template <typename real, int DIM, int EQ>
-__device__ __forceinline__ void flux_rt(const real *U, int d, const real *par, real *F, real &lam)
+// flux along D and wave speed of a state U held in registers (same rounding
+// as the LDS copies made in phase 1)
+template <typename real, int DIM, int EQ, int D>
+__device__ __forceinline__ void flux_of(const real *U, const real *par, real *F, real &lam)
 {
     if constexpr (EQ == 0) {
 #pragma clang fp contract(off)
-        const real a = sel(d, par[0], par[1], par[2]);
-        F[0] = a * U[0];
-        lam = fabs(a);
+        F[0] = par[D] * U[0];
+        lam = fabs(par[D]);
     } else {
         const real c = par[0];
         const real c2 = c * c;
         const real rinv = recip(U[0]);
-        const real md = sel(d, U[1], U[DIM > 1 ? 2 : 1], U[DIM > 2 ? 3 : 1]);
-        F[0] = md;
+        F[0] = U[1 + D];
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
-            const real mk = U[1 + k];
-            const bool le = d <= k;
-            F[1 + k] = sym_flux(le ? md : mk, le ? mk : md, U[0], rinv, c2, d == k);
+            const int a = D < k ? D : k, b = D < k ? k : D;
+            F[1 + k] = sym_flux(U[1 + a], U[1 + b], U[0], rinv, c2, a == b);
         }
-        lam = wave_speed(md, rinv, c);
+        lam = wave_speed(U[1 + D], rinv, c);
     }
 }
 
@@ -158,23 +153,26 @@ struct Arr<real, true> {
         r = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0,
                                               (int)(uint32_t(nvar) * vbytes), 0x00020000);
     }
+    // POL: cache-policy bits of the buffer instruction (2 = non-temporal on gfx950)
+    template <int POL = 0>
     __device__ __forceinline__ real ld(int v, idx_t node) const
     {
         if constexpr (sizeof(real) == 8)
             return __builtin_bit_cast(real, __builtin_amdgcn_raw_buffer_load_b64(
-                                                r, node * (uint32_t)sizeof(real), v * vbytes, 0));
+                                                r, node * (uint32_t)sizeof(real), v * vbytes, POL));
         else
             return __builtin_bit_cast(real, __builtin_amdgcn_raw_buffer_load_b32(
-                                                r, node * (uint32_t)sizeof(real), v * vbytes, 0));
+                                                r, node * (uint32_t)sizeof(real), v * vbytes, POL));
     }
+    template <int POL = 0>
     __device__ __forceinline__ void st(int v, idx_t node, real x) const
     {
         if constexpr (sizeof(real) == 8)
             __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r,
-                                                  node * (uint32_t)sizeof(real), v * vbytes, 0);
+                                                  node * (uint32_t)sizeof(real), v * vbytes, POL);
         else
             __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), r,
-                                                  node * (uint32_t)sizeof(real), v * vbytes, 0);
+                                                  node * (uint32_t)sizeof(real), v * vbytes, POL);
     }
 };
 
@@ -185,15 +183,25 @@ struct Arr<real, false> {
     int64_t stride;
     __device__ __forceinline__ Arr(const void *ptr, int64_t s, int)
         : p(static_cast<real *>(const_cast<void *>(ptr))), stride(s) {}
-    __device__ __forceinline__ real ld(int v, idx_t node) const { return p[v * stride + node]; }
-    __device__ __forceinline__ void st(int v, idx_t node, real x) const { p[v * stride + node] = x; }
+    template <int POL = 0>
+    __device__ __forceinline__ real ld(int v, idx_t node) const
+    {
+        if constexpr (POL != 0) return __builtin_nontemporal_load(p + v * stride + node);
+        else return p[v * stride + node];
+    }
+    template <int POL = 0>
+    __device__ __forceinline__ void st(int v, idx_t node, real x) const
+    {
+        if constexpr (POL != 0) __builtin_nontemporal_store(x, p + v * stride + node);
+        else p[v * stride + node] = x;
+    }
 };
 
-template <typename real, int DIM, int N, int EQ, bool BUF>
-__global__ void __launch_bounds__((Geo<DIM, N>::THREADS)) __attribute__((amdgpu_waves_per_eu(4)))
+template <typename real, int DIM, int N, int EQ, bool BUF, int SPOL = 0, int YPOL = 0, int TM = 1>
+__global__ void __launch_bounds__((Geo<DIM, N, TM>::THREADS)) __attribute__((amdgpu_waves_per_eu(4)))
 stage_kernel(const StageParams p)
 {
-    using G = Geo<DIM, N>;
+    using G = Geo<DIM, N, TM>;
     constexpr int N1 = G::N1, NP = G::NP, NF1 = G::NF1, EPB = G::EPB, TN = G::TN;
     constexpr int THREADS = G::THREADS, NF = G::NF, NL = G::NL;
     constexpr int NV = Vars<EQ, DIM>::NV, NSYM = Vars<EQ, DIM>::NSYM;
@@ -238,7 +246,7 @@ stage_kernel(const StageParams p)
     for (uint32_t vb = blockIdx.x; vb < p.ntiles32; vb += gridDim.x) {
         // ---- tile coordinates (XCD-contiguous numbering, magic divisions)
         const uint32_t xb = vb & (kXcds - 1), jb = vb / kXcds;
-        const uint32_t L = xb * p.xq + (xb < p.xr ? xb : p.xr) + jb;
+        const uint32_t L = p.plain_order ? vb : xb * p.xq + (xb < p.xr ? xb : p.xr) + jb;
         int64_t tx, ey, ez;
         if constexpr (DIM == 1) {
             tx = L; ey = 0; ez = 0;
@@ -258,11 +266,20 @@ stage_kernel(const StageParams p)
         const int nact = (int)((K0 - ex0) < EPB ? (K0 - ex0) : EPB);
         const int64_t ebase = K0 * (ey + K1 * ez);     // element index of (0, ey, ez)
 
-        // global element of the side of face point (w0, ps) that lies outside the tile
-        auto outside_elem = [&](uint32_t w0, uint32_t ps, bool lglob) -> int64_t {
-            const int d = int(w0 & 3u), kind = int((w0 >> 18) & 3u);
+        // Face point fields (see dg_tables.cpp): w0 = d | own_slot << 2 |
+        // (other_slot+1) << 10 | other_is_lower << 18 | kind << 19,
+        // w1 = own_node | other_node << 16, w2 = plane or slot, w3 = lift slots.
+        auto face_valid = [&](uint32_t w0, uint32_t ps) {
+            return ((w0 >> 19) & 3u) == 0 ? ps <= uint32_t(nact) : ps < uint32_t(nact);
+        };
+        auto other_outside = [&](uint32_t w0, uint32_t ps) {
+            return ((w0 >> 10) & 0xffu) == 0 || (((w0 >> 19) & 3u) == 0 && ps == uint32_t(nact));
+        };
+        // element holding the other side when it lies outside the tile
+        auto outside_elem = [&](uint32_t w0, uint32_t ps) -> int64_t {
+            const int d = int(w0 & 3u), kind = int((w0 >> 19) & 3u);
             if (kind == 0) {
-                int64_t ex = lglob ? ex0 - 1 : ex0 + nact;
+                int64_t ex = ((w0 >> 18) & 1u) ? ex0 - 1 : ex0 + nact;
                 if (ex < 0) ex += K0;
                 if (ex >= K0) ex -= K0;
                 return ebase + ex;
@@ -280,27 +297,13 @@ stage_kernel(const StageParams p)
             }
             return ex0 + int64_t(ps) + K0 * (yy + K1 * zz);
         };
-        // does face point (w0, ps) exist in this tile, and which sides are outside it
-        auto face_sides = [&](uint32_t w0, uint32_t ps, bool &valid, bool &lglob, bool &rglob) {
-            const int kind = int((w0 >> 18) & 3u);
-            const uint32_t lsl = (w0 >> 2) & 0xffu, rsl = (w0 >> 10) & 0xffu;
-            valid = kind == 0 ? ps <= uint32_t(nact) : ps < uint32_t(nact);
-            lglob = lsl == 0;
-            rglob = kind == 0 ? ps == uint32_t(nact) : rsl == 0;
-        };
 
         // ---- prefetch the outside state of this thread's first face point
         real g[NV];
-        if (tid < NF) {
-            bool valid, lglob, rglob;
-            face_sides(fw0, fw2, valid, lglob, rglob);
-            if (valid && (lglob || rglob)) {
-                const int64_t en = outside_elem(fw0, fw2, lglob);
-                const uint32_t node = lglob ? (fw1 & 0xffffu) : (fw1 >> 16);
-                const idx_t gn = idx_t(en * NP + node);
+        if (tid < NF && face_valid(fw0, fw2) && other_outside(fw0, fw2)) {
+            const idx_t gn = idx_t(outside_elem(fw0, fw2) * NP + (fw1 >> 16));
 #pragma unroll
-                for (int v = 0; v < NV; ++v) g[v] = yin.ld(v, gn);
-            }
+            for (int v = 0; v < NV; ++v) g[v] = yin.ld(v, gn);
         }
 
         // ---- phase 1: state, 1/rho and flux tensor into LDS
@@ -310,7 +313,7 @@ stage_kernel(const StageParams p)
         real y[NV];
         if (active) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) y[v] = yin.ld(v, gi);
+            for (int v = 0; v < NV; ++v) y[v] = yin.template ld<YPOL>(v, gi);
 #pragma unroll
             for (int v = 0; v < NV; ++v) sY[v][ln] = y[v];
             if constexpr (EQ == 1) {
@@ -325,7 +328,12 @@ stage_kernel(const StageParams p)
         }
         __syncthreads();
 
-        // ---- phase 2: Lax-Friedrichs flux at the tile's face points, lifts to LDS
+        // ---- phase 2: Lax-Friedrichs flux at the tile's face points, lifts to LDS.
+        // With sigma = -1 when the other side is the lower one,
+        //   Fhat = 1/2 [(F_own + F_oth) - (sigma alpha)(U_oth - U_own)]
+        // is eq. LF with (U^-, U^+) = (lower, upper); two tiles sharing a face
+        // evaluate it with the roles swapped and get the same bits (the sum
+        // commutes and both factors of the product change sign exactly).
         for (int f = tid; f < NF; f += THREADS) {
             uint32_t w0 = fw0, w1 = fw1, w2 = fw2, w3 = fw3;
             if (f >= THREADS) {
@@ -334,52 +342,57 @@ stage_kernel(const StageParams p)
                 w2 = p.ftab[4 * f + 2];
                 w3 = p.ftab[4 * f + 3];
             }
-            bool valid, lglob, rglob;
-            face_sides(w0, w2, valid, lglob, rglob);
-            if (!valid) continue;
-            const int d = int(w0 & 3u);
-            const int lslot = int((w0 >> 2) & 0xffu) - 1, rslot = int((w0 >> 10) & 0xffu) - 1;
-            const int lnode = int(w1 & 0xffffu), rnode = int(w1 >> 16);
-            if (f >= THREADS && (lglob || rglob)) {
-                const int64_t en = outside_elem(w0, w2, lglob);
-                const idx_t gn = idx_t(en * NP + (lglob ? lnode : rnode));
+            if (!face_valid(w0, w2)) continue;
+            const bool oglob = other_outside(w0, w2);
+            if (f >= THREADS && oglob) {
+                const idx_t gn = idx_t(outside_elem(w0, w2) * NP + (w1 >> 16));
 #pragma unroll
                 for (int v = 0; v < NV; ++v) g[v] = yin.ld(v, gn);
             }
-            real UL[NV], UR[NV], FL[NV], FR[NV], lamL, lamR;
-            auto side_state = [&](bool glob, int sl, int node, real *U, real *F, real &lam) {
-                if (!glob) {
-                    const int q = sl * NP + node;
+            const int own_q = int((w0 >> 2) & 0xffu) * NP + int(w1 & 0xffffu);
+            const int oth_q = (int((w0 >> 10) & 0xffu) - 1) * NP + int(w1 >> 16);
+            const bool oth_lower = (w0 >> 18) & 1u;
+            const int own_l = int(w3 & 0xffffu), oth_l = int(w3 >> 16);
+            auto face = [&](auto dconst) {
+                constexpr int D = decltype(dconst)::value;
+                real Uo[NV], Fo[NV], Ut[NV], Ft[NV], lo, lt;
+                auto from_lds = [&](int q, real *U, real *F, real &lam) {
 #pragma unroll
                     for (int v = 0; v < NV; ++v) U[v] = sY[v][q];
                     if constexpr (EQ == 0) {
 #pragma clang fp contract(off)
-                        const real a = sel(d, par[0], par[1], par[2]);
-                        F[0] = a * U[0];
-                        lam = fabs(a);
+                        F[0] = par[D] * U[0];
+                        lam = fabs(par[D]);
                     } else {
-                        F[0] = sY[1 + d][q];
+                        F[0] = U[1 + D];
 #pragma unroll
-                        for (int k = 0; k < DIM; ++k) F[1 + k] = sP[sym_index(d, k, DIM)][q];
+                        for (int k = 0; k < DIM; ++k) F[1 + k] = sP[sym_index(D, k, DIM)][q];
                         lam = wave_speed(F[0], sRi[q], par[0]);
                     }
-                } else {
+                };
+                from_lds(own_q, Uo, Fo, lo);
+                if (oglob) {
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) U[v] = g[v];
-                    flux_rt<real, DIM, EQ>(U, d, par, F, lam);
+                    for (int v = 0; v < NV; ++v) Ut[v] = g[v];
+                    flux_of<real, DIM, EQ, D>(Ut, par, Ft, lt);
+                } else {
+                    from_lds(oth_q, Ut, Ft, lt);
+                }
+                const real alpha = lo > lt ? lo : lt;
+                const real sa = oth_lower ? -alpha : alpha;
+                const real sl = rdx2[D] * INVW0;
+                const real so = oth_lower ? sl : -sl;     // lift sign of the own side
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    const real fh = real(0.5) * ((Fo[v] + Ft[v]) - sa * (Ut[v] - Uo[v]));
+                    sL[v][own_l] = so * (fh - Fo[v]);
+                    if (!oglob) sL[v][oth_l] = -so * (fh - Ft[v]);
                 }
             };
-            side_state(lglob, lslot, lnode, UL, FL, lamL);
-            side_state(rglob, rslot, rnode, UR, FR, lamR);
-            const real alpha = lamL > lamR ? lamL : lamR;
-            const real s = sel(d, rdx2[0], rdx2[1], rdx2[2]) * INVW0;
-            const int liftL = int(w3 & 0xffffu), liftR = int(w3 >> 16);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                const real fh = real(0.5) * ((FL[v] + FR[v]) - alpha * (UR[v] - UL[v]));
-                if (!lglob) sL[v][liftL] = -s * (fh - FL[v]);
-                if (!rglob) sL[v][liftR] = s * (fh - FR[v]);
-            }
+            const int d = int(w0 & 3u);
+            if (d == 0) face(std::integral_constant<int, 0>());
+            if constexpr (DIM > 1) if (d == 1) face(std::integral_constant<int, 1>());
+            if constexpr (DIM > 2) if (d == 2) face(std::integral_constant<int, 2>());
         }
         __syncthreads();
 
@@ -427,12 +440,12 @@ stage_kernel(const StageParams p)
             if (p.nin > 0) {
                 const A in0(p.in0, p.stride, NV);
 #pragma unroll
-                for (int v = 0; v < NV; ++v) a0[v] = in0.ld(v, gi);
+                for (int v = 0; v < NV; ++v) a0[v] = in0.template ld<SPOL>(v, gi);
             }
             if (p.nin > 1) {
                 const A in1(p.in1, p.stride, NV);
 #pragma unroll
-                for (int v = 0; v < NV; ++v) a1[v] = in1.ld(v, gi);
+                for (int v = 0; v < NV; ++v) a1[v] = in1.template ld<SPOL>(v, gi);
             }
 #pragma unroll
             for (int o = 0; o < 2; ++o) {
@@ -446,7 +459,7 @@ stage_kernel(const StageParams p)
                         if (p.nin > 0) val += c0 * a0[v];
                         if (p.nin > 1) val += c1 * a1[v];
                         val += cr * R[v];
-                        out.st(v, gi, val);
+                        out.template st<SPOL>(v, gi, val);
                     }
                 }
             }

@@ -9,13 +9,16 @@
 //   f >= NFX: direction d = 1, 2: the lower (side 0) or upper (side 1) face of
 //             slot s at tangential node t; the other side is the neighbouring
 //             element along d (global memory).
-// Entry (4 x uint32):
-//   w0 = d | (lslot+1) << 2 | (rslot+1) << 10 | kind << 18
-//        (slot+1 = 0: that side is not in the tile; kind 0 x-plane,
+// Each face point has an "own" side inside the tile and an "other" side
+// (inside the tile only for x-planes between two tile slots). Entry (4 x uint32):
+//   w0 = d | own_slot << 2 | (other_slot+1) << 10 | other_is_lower << 18 | kind << 19
+//        (other_slot+1 = 0: the other side lies outside the tile; kind 0 x-plane,
 //         1 lower face of slot s, 2 upper face of slot s)
-//   w1 = lnode | rnode << 16   node of the left/right side inside its element
-//   w2 = pl or s               (plane or slot, for the ragged-tile test)
-//   w3 = liftL | liftR << 16   lift slots written for the in-tile sides
+//   w1 = own_node | other_node << 16   node of each side inside its element
+//   w2 = pl or s                       (plane or slot, for the ragged-tile test)
+//   w3 = own_lift | other_lift << 16   lift slots of the two sides
+// For x-planes the table assumes a full tile; the kernel treats plane nact of
+// a ragged tile (nact < EPB active slots) as having its other side outside.
 #include <cstdint>
 #include <vector>
 
@@ -40,17 +43,21 @@ void build_face_table(int dim, int N, int epb, uint32_t *tab)
         return (uint32_t)(((d * epb + slot) * 2 + side) * NF1 + t);
     };
     for (int f = 0; f < NF; ++f) {
-        uint32_t d, kind, ps, lnode, rnode, liftL = 0xffff, liftR = 0xffff;
-        int lslot, rslot;
+        uint32_t d, kind, ps, own_node, oth_node, own_lift, oth_lift = 0xffff, oth_lower;
+        int own_slot, oth_slot;
         if (f < NFX) {
             const int pl = f / NF1, t = f % NF1;
             d = 0; kind = 0; ps = (uint32_t)pl;
-            lslot = pl - 1;
-            rslot = pl < epb ? pl : -1;
-            lnode = (uint32_t)(N + N1 * t);
-            rnode = (uint32_t)(N1 * t);
-            if (lslot >= 0) liftL = lift(0, lslot, 1, t);
-            if (rslot >= 0) liftR = lift(0, rslot, 0, t);
+            const uint32_t lnode = (uint32_t)(N + N1 * t), rnode = (uint32_t)(N1 * t);
+            if (pl == 0) {            // own: slot 0 (upper side), other: tile to the left
+                own_slot = 0; own_node = rnode; own_lift = lift(0, 0, 0, t);
+                oth_slot = -1; oth_node = lnode; oth_lower = 1;
+            } else {                  // own: slot pl-1 (lower side), other: slot pl or outside
+                own_slot = pl - 1; own_node = lnode; own_lift = lift(0, pl - 1, 1, t);
+                oth_node = rnode; oth_lower = 0;
+                oth_slot = pl < epb ? pl : -1;
+                if (oth_slot >= 0) oth_lift = lift(0, pl, 0, t);
+            }
         } else {
             const int g = f - NFX;
             d = (uint32_t)(1 + g / NFO);
@@ -60,20 +67,21 @@ void build_face_table(int dim, int N, int epb, uint32_t *tab)
             const uint32_t nlo = d == 1 ? (uint32_t)(ta + N1 * (0 + N1 * tb)) : (uint32_t)(ta + N1 * (tb + N1 * 0));
             const uint32_t nhi = d == 1 ? (uint32_t)(ta + N1 * (N + N1 * tb)) : (uint32_t)(ta + N1 * (tb + N1 * N));
             ps = (uint32_t)s;
-            lnode = nhi;
-            rnode = nlo;
-            if (side == 0) {
-                kind = 1; lslot = -1; rslot = s;
-                liftR = lift((int)d, s, 0, t);
-            } else {
-                kind = 2; lslot = s; rslot = -1;
-                liftL = lift((int)d, s, 1, t);
+            own_slot = s;
+            oth_slot = -1;
+            if (side == 0) {          // lower face: own is the upper side of the face
+                kind = 1; own_node = nlo; oth_node = nhi; oth_lower = 1;
+                own_lift = lift((int)d, s, 0, t);
+            } else {                  // upper face: own is the lower side of the face
+                kind = 2; own_node = nhi; oth_node = nlo; oth_lower = 0;
+                own_lift = lift((int)d, s, 1, t);
             }
         }
-        tab[4 * f + 0] = d | (uint32_t)(lslot + 1) << 2 | (uint32_t)(rslot + 1) << 10 | kind << 18;
-        tab[4 * f + 1] = lnode | rnode << 16;
+        tab[4 * f + 0] = d | (uint32_t)own_slot << 2 | (uint32_t)(oth_slot + 1) << 10 | oth_lower << 18 |
+                         kind << 19;
+        tab[4 * f + 1] = own_node | oth_node << 16;
         tab[4 * f + 2] = ps;
-        tab[4 * f + 3] = liftL | liftR << 16;
+        tab[4 * f + 3] = own_lift | oth_lift << 16;
     }
 }
 
