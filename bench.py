@@ -2,6 +2,7 @@
 """Benchmark of the fused NDG RHS + RK4 stage path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 4] [--precision fp64]
+    python bench.py --serve [--requests 2000] [--time-scale 0.01] [--rates 1]
 
 A step is one classical RK4 step (four fused RHS + stage launches) over the
 whole mesh of the chosen workload; default: 3-D isothermal Euler, 64^3
@@ -19,6 +20,14 @@ timed region. Prints one JSON line:
                (profiles/), null when the kernel changed since they were taken
   cpu_baseline the CPU oracle (FP64, OpenMP) timed on this host on full-mesh
                RK4 steps of the same workload (a bounded sample, >= 1 step)
+
+--serve measures the continuous-batching server on the seeded request stream
+(1-D/2-D advection and 2-D isothermal Euler, N in 1..7, K log-uniform in
+[16, 256^2], final times uniform in [0.1, 1] x time-scale, FP64, RK4):
+first at saturation (every request arrives at time 0) for the capacity C in
+solves/s, then with Poisson arrivals at each rate multiple of C; each run is
+repeated one solve at a time (FIFO, dg_step alone) on the same GPU. Prints one
+JSON line with solves/s and p50/p99 latency (completion - arrival) per run.
 """
 from __future__ import annotations
 
@@ -83,6 +92,72 @@ def cpu_baseline(w, U0, dt, budget_s: float):
                       f"{el:.1f} s, FP64, OpenMP over elements"}
 
 
+def serve_main(a):
+    import math
+    import torch
+    from paper_2510_05254_amd import serve
+
+    def log(msg):
+        print(f"[serve] {msg}", file=sys.stderr, flush=True)
+
+    torch.cuda.init()
+    arena = int(a.arena_gib * (1 << 30))
+    reqs = serve.request_stream(a.requests, 1.0, time_scale=a.time_scale)
+    t0 = time.perf_counter()
+    prep = {r.rid: serve.prepare(r) for r in reqs}
+    log(f"prepared {len(reqs)} requests in {time.perf_counter() - t0:.1f} s")
+    upd = sum(r.unknowns * 4 * prep[r.rid][2] for r in reqs)
+
+    # untimed warm-up over a small stream (kernel loading, first launches)
+    wreqs = serve.request_stream(40, 1.0, seed=1, time_scale=0.001, kmax=1024)
+    wprep = {r.rid: serve.prepare(r) for r in wreqs}
+    with serve.Server(arena, chunk=a.chunk, graph=not a.no_graph) as srv:
+        srv.serve(serve.with_rate(wreqs, math.inf, 1), wprep)
+    serve.serve_sequential(serve.with_rate(wreqs, math.inf, 1), wprep, 1 << 30)
+
+    def run_batched(rate, seed):
+        with serve.Server(arena, chunk=a.chunk, graph=not a.no_graph) as srv:
+            done, rej, wall = srv.serve(serve.with_rate(reqs, rate, seed), prep)
+        out = serve.summarize(done, wall)
+        out["rejected"] = len(rej)
+        log(f"batched rate={rate:.4g}: {json.dumps(out)}")
+        return out
+
+    def run_seq(rate, seed):
+        done, rej, wall = serve.serve_sequential(serve.with_rate(reqs, rate, seed), prep, arena)
+        out = serve.summarize(done, wall)
+        out["rejected"] = len(rej)
+        log(f"sequential rate={rate:.4g}: {json.dumps(out)}")
+        return out
+
+    cap_b = run_batched(math.inf, 0)
+    cap_s = run_seq(math.inf, 0)
+    C = cap_b["solves_per_s"]
+    runs = []
+    for i, f in enumerate(float(x) for x in a.rates.split(",") if x):
+        rate = f * C
+        runs.append({"rate_multiple": f, "rate_per_s": rate,
+                     "batched": run_batched(rate, 100 + i), "sequential": run_seq(rate, 100 + i)})
+    out = {
+        "metric": "served solves/s with p50/p99 latency",
+        "value": C,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"served_stream_{a.requests}req_timescale{a.time_scale:g}",
+                   "requests": a.requests, "time_scale": a.time_scale, "rk": 4,
+                   "arena_gib": a.arena_gib, "chunk": a.chunk, "graph": not a.no_graph,
+                   "dof_updates": upd},
+        "capacity": {"batched": cap_b, "sequential": cap_s,
+                     "speedup": C / cap_s["solves_per_s"]},
+        "rates": runs,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,11 +168,21 @@ def main():
     ap.add_argument("--rk", type=int, choices=[3, 4], default=4)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve", action="store_true", help="served-stream benchmark")
+    ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--time-scale", type=float, default=0.01)
+    ap.add_argument("--rates", default="1", help="comma-separated multiples of capacity")
+    ap.add_argument("--arena-gib", type=float, default=32.0)
+    ap.add_argument("--chunk", type=int, default=32)
+    ap.add_argument("--no-graph", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the sharding design is described in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+    if a.serve:
+        serve_main(a)
+        return
 
     import torch
     from paper_2510_05254_amd import dg

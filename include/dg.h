@@ -55,6 +55,7 @@ extern "C" {
 #endif
 
 typedef struct dg_solver dg_solver;
+typedef struct dg_batch dg_batch;
 
 enum dg_status {
     DG_OK = 0,
@@ -155,6 +156,55 @@ int dg_synchronize(dg_solver *h);
 
 /* The solver's hipStream_t (as void*), for stream-ordered interop. */
 void *dg_stream(const dg_solver *h);
+
+/* ---------------------------------------------------------------------------
+ * Batched stepping (many solves advanced together; the method per solve is
+ * unchanged: every member takes the same RK steps it would take alone).
+ *
+ * A batch advances its member solvers on the batch's stream. Each "tick" is
+ * one RK step of every active member; all members that share a kernel class
+ * (precision, equation, dim, N) and scheme are advanced by one launch per RK
+ * stage, whatever their meshes, arrays and time steps, so many small solves
+ * fill the GPU together. Members keep their own state arrays; results are
+ * bitwise those of dg_step on the same member alone.
+ * ------------------------------------------------------------------------ */
+
+#define DG_BATCH_GRAPH 1   /* replay ticks from a captured hipGraph of one tick
+                              (captured at the first run of >= 4 ticks after a
+                              membership change; shorter runs launch directly) */
+
+/* Create an empty batch on the current device. hip_stream: hipStream_t to run
+ * on, or NULL for a library stream. flags: 0 or DG_BATCH_GRAPH. */
+int dg_batch_create(void *hip_stream, int flags, dg_batch **out);
+
+/* Wait for the batch's work and release it; members are released from it
+ * (their handles stay valid). NULL is accepted. */
+int dg_batch_destroy(dg_batch *b);
+
+/* Add solver h (state set, on the batch's device, not in another batch) to
+ * run nsteps >= 1 more steps of scheme rk (DG_RK3 or DG_RK4; DG_ENOTSUP for
+ * DG_RK6) with step dt > 0. While a member, h must not be stepped or have its
+ * state set directly (DG_ESTATE); dg_get_state / dg_l2_error / dg_mass on it
+ * are stream-ordered after the batch work enqueued so far. */
+int dg_batch_add(dg_batch *b, dg_solver *h, int rk, double dt, int64_t nsteps);
+
+/* Remove member h (finished or not); its remaining steps are dropped. */
+int dg_batch_remove(dg_batch *b, dg_solver *h);
+
+/* Enqueue s = min(max_steps, smallest remaining step count of the active
+ * members) ticks and return s in *steps_done (0 when no member is active).
+ * Members whose remaining count reaches 0 become inactive (they stay members
+ * until removed). Asynchronous. */
+int dg_batch_run(dg_batch *b, int64_t max_steps, int64_t *steps_done);
+
+/* Steps member h still has to run. */
+int dg_batch_remaining(const dg_batch *b, const dg_solver *h, int64_t *remaining);
+
+/* Number of members and of active members. Either pointer may be NULL. */
+int dg_batch_size(const dg_batch *b, int *members, int *active);
+
+/* Wait for all work enqueued on the batch's stream. */
+int dg_batch_synchronize(dg_batch *b);
 
 /* Message for the calling thread's last non-OK return ("" if none). */
 const char *dg_last_error(void);

@@ -33,8 +33,10 @@
 using namespace dg;
 
 namespace {
-
 thread_local std::string g_last_error;
+}
+
+namespace dg {
 
 int fail(int code, const std::string &msg)
 {
@@ -42,18 +44,12 @@ int fail(int code, const std::string &msg)
     return code;
 }
 
-constexpr size_t kAlign = 256;
-constexpr int64_t kReduceBlocks = 1024;
-constexpr size_t kFaceTableBytes = 16384;
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(DG_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
 
 size_t round_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-
-struct Layout {
-    size_t tables = 0;      // D (real), w (double), reduction partials
-    size_t array = 0;       // one state array
-    size_t base = 0;        // tables + 4 arrays (RK3/RK4)
-    size_t rk6 = 0;         // base + 5 more arrays (RK6 k-store)
-};
 
 Layout layout_for(int dim, int N, const int64_t *K, int eq, int prec)
 {
@@ -98,46 +94,6 @@ int validate(int dim, int N, const int64_t *K, int eq, const double *params, int
     return DG_OK;
 }
 
-int hip_fail(hipError_t e, const char *what)
-{
-    return fail(DG_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
-}
-
-#define DG_HIP(call, what)                          \
-    do {                                            \
-        hipError_t e_ = (call);                     \
-        if (e_ != hipSuccess) return hip_fail(e_, what); \
-    } while (0)
-
-}  // namespace
-
-struct dg_solver {
-    int dim = 0, N = 0, eq = 0, prec = 0, nvar = 0, n1 = 0, np = 0;
-    int64_t K[3] = {1, 1, 1};
-    int64_t nodes = 0, unknowns = 0;
-    double par[3] = {0, 0, 0};
-    double xi[kMaxNP1], w[kMaxNP1], D[kMaxNP1 * kMaxNP1];
-    int device = 0;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    char *ws = nullptr;
-    size_t ws_bytes = 0;
-    bool own_ws = false;
-    Layout lay;
-    void *Dtab = nullptr;
-    double *wtab = nullptr;
-    uint32_t *ftab = nullptr;
-    double *partial = nullptr;
-    void *U = nullptr, *A = nullptr, *Ya = nullptr, *Yb = nullptr;
-    void *kx[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // RK6 k3..k7
-    char *rk6_mem = nullptr;        // library-owned RK6 extension
-    bool has_state = false;
-    StageFn stage = nullptr;
-    int epb = 0;
-    int64_t tiles_x = 0, slab = 1, ntiles = 0, grid = 0;
-};
-
-namespace {
 
 int select_device(const dg_solver *h)
 {
@@ -169,32 +125,82 @@ StageParams base_params(const dg_solver *h)
     return p;
 }
 
-// One fused stage: R = F(yin); out_o = cy yin + c0 in0 + c1 in1 + cr R.
-struct Out {
-    void *ptr;
-    double cy, c0, c1, cr;
-};
+int stage_count(int rk) { return rk == DG_RK4 ? 4 : rk == DG_RK3 ? 3 : rk == DG_RK6 ? 7 : 0; }
 
-int run_stage(dg_solver *h, const void *yin, const void *in0, const void *in1, int nin,
-              std::initializer_list<Out> outs)
+namespace {
+void set_out(StageParams &p, int o, void *ptr, double cy, double c0, double c1, double cr)
+{
+    (o == 0 ? p.out0 : p.out1) = ptr;
+    p.cy[o] = cy;
+    p.c0[o] = c0;
+    p.c1[o] = c1;
+    p.cr[o] = cr;
+    p.nout = o + 1;
+}
+}  // namespace
+
+// Fused-stage programs of the RK3 and RK4 schedules (see the file comment):
+// stage s reads yin (and in0/in1), writes out0/out1 = cy yin + c0 in0 + c1 in1 + cr R.
+StageParams stage_program(const dg_solver *h, int rk, int s, double dt)
+{
+    StageParams p = base_params(h);
+    if (rk == DG_RK4) {
+        switch (s) {
+        case 0:
+            p.yin = h->U; p.nin = 0;
+            set_out(p, 0, h->Yb, 1.0, 0.0, 0.0, dt / 2);
+            break;
+        case 1:
+            p.yin = h->Yb; p.in0 = h->U; p.nin = 1;
+            set_out(p, 0, h->A, 1.0 / 3.0, 2.0 / 3.0, 0.0, dt / 3);
+            set_out(p, 1, h->Ya, 0.0, 1.0, 0.0, dt / 2);
+            break;
+        case 2:
+            p.yin = h->Ya; p.in0 = h->U; p.in1 = h->A; p.nin = 2;
+            set_out(p, 0, h->A, 0.0, 0.0, 1.0, dt / 3);
+            set_out(p, 1, h->Yb, 0.0, 1.0, 0.0, dt);
+            break;
+        default:
+            p.yin = h->Yb; p.in0 = h->A; p.nin = 1;
+            set_out(p, 0, h->U, 0.0, 1.0, 0.0, dt / 6);
+            break;
+        }
+    } else {   // RK3, Heun
+        switch (s) {
+        case 0:
+            p.yin = h->U; p.nin = 0;
+            set_out(p, 0, h->Ya, 1.0, 0.0, 0.0, dt / 3);
+            set_out(p, 1, h->A, 1.0, 0.0, 0.0, dt / 4);
+            break;
+        case 1:
+            p.yin = h->Ya; p.in0 = h->U; p.nin = 1;
+            set_out(p, 0, h->Yb, 0.0, 1.0, 0.0, 2.0 * dt / 3);
+            break;
+        default:
+            p.yin = h->Yb; p.in0 = h->A; p.nin = 1;
+            set_out(p, 0, h->U, 0.0, 1.0, 0.0, 3.0 * dt / 4);
+            break;
+        }
+    }
+    return p;
+}
+
+namespace {
+
+int launch(dg_solver *h, const StageParams &p)
+{
+    DG_HIP(h->stage(p, h->grid, h->stream), "stage kernel launch");
+    return DG_OK;
+}
+
+// RK6 k-store stage: k = dt F(yin)
+int run_k_stage(dg_solver *h, const void *yin, void *k, double dt)
 {
     StageParams p = base_params(h);
     p.yin = yin;
-    p.in0 = in0;
-    p.in1 = in1;
-    p.nin = nin;
-    int o = 0;
-    for (const Out &x : outs) {
-        (o == 0 ? p.out0 : p.out1) = x.ptr;
-        p.cy[o] = x.cy;
-        p.c0[o] = x.c0;
-        p.c1[o] = x.c1;
-        p.cr[o] = x.cr;
-        ++o;
-    }
-    p.nout = o;
-    DG_HIP(h->stage(p, h->grid, h->stream), "stage kernel launch");
-    return DG_OK;
+    p.nin = 0;
+    set_out(p, 0, k, 0.0, 0.0, 0.0, dt);
+    return launch(h, p);
 }
 
 int ensure_rk6(dg_solver *h)
@@ -237,29 +243,13 @@ int run_combine(dg_solver *h, void *out, const void *base, double a_base,
     return DG_OK;
 }
 
-int step_rk4(dg_solver *h, double dt)
+int step_rk34(dg_solver *h, int rk, double dt)
 {
-    int rc;
-    if ((rc = run_stage(h, h->U, nullptr, nullptr, 0, {{h->Yb, 1.0, 0.0, 0.0, dt / 2}})))
-        return rc;
-    if ((rc = run_stage(h, h->Yb, h->U, nullptr, 1,
-                        {{h->A, 1.0 / 3.0, 2.0 / 3.0, 0.0, dt / 3}, {h->Ya, 0.0, 1.0, 0.0, dt / 2}})))
-        return rc;
-    if ((rc = run_stage(h, h->Ya, h->U, h->A, 2,
-                        {{h->A, 0.0, 0.0, 1.0, dt / 3}, {h->Yb, 0.0, 1.0, 0.0, dt}})))
-        return rc;
-    return run_stage(h, h->Yb, h->A, nullptr, 1, {{h->U, 0.0, 1.0, 0.0, dt / 6}});
-}
-
-int step_rk3(dg_solver *h, double dt)
-{
-    int rc;
-    if ((rc = run_stage(h, h->U, nullptr, nullptr, 0,
-                        {{h->Ya, 1.0, 0.0, 0.0, dt / 3}, {h->A, 1.0, 0.0, 0.0, dt / 4}})))
-        return rc;
-    if ((rc = run_stage(h, h->Ya, h->U, nullptr, 1, {{h->Yb, 0.0, 1.0, 0.0, 2.0 * dt / 3}})))
-        return rc;
-    return run_stage(h, h->Yb, h->A, nullptr, 1, {{h->U, 0.0, 1.0, 0.0, 3.0 * dt / 4}});
+    for (int st = 0; st < stage_count(rk); ++st) {
+        int rc = launch(h, stage_program(h, rk, st, dt));
+        if (rc) return rc;
+    }
+    return DG_OK;
 }
 
 // Luther's RK6 (eq. RK6): Y_s = U + (sum_j num[s][j] k_j) / den[s].
@@ -305,7 +295,7 @@ int step_rk6(dg_solver *h, double dt)
     int rc;
     for (int s = 0; s < 7; ++s) {
         const void *ys = s == 0 ? h->U : Y;
-        if ((rc = run_stage(h, ys, nullptr, nullptr, 0, {{k[s], 0.0, 0.0, 0.0, dt}}))) return rc;
+        if ((rc = run_k_stage(h, ys, k[s], dt))) return rc;
         std::vector<std::pair<const void *, double>> src;
         if (s < 6) {
             for (int j = 0; j <= s; ++j)
@@ -388,6 +378,7 @@ void free_solver(dg_solver *h)
 }
 
 }  // namespace
+}  // namespace dg
 
 extern "C" {
 
@@ -540,6 +531,7 @@ int dg_create(int dim, int N, const int64_t *K, int equation, const double *para
 
 int dg_destroy(dg_solver *h)
 {
+    if (h && h->batch) (void)dg_batch_remove(h->batch, h);
     free_solver(h);
     return DG_OK;
 }
@@ -566,6 +558,7 @@ int dg_get_axis_coords(const dg_solver *h, int axis, double *x, int64_t count)
 int dg_set_state(dg_solver *h, const double *u, int64_t count)
 {
     if (!h || !u) return fail(DG_EINVAL, "NULL argument");
+    if (h->batch) return fail(DG_ESTATE, "solver belongs to a batch");
     int rc = check_count(h, count);
     if (rc || (rc = select_device(h))) return rc;
     if (h->prec == DG_FP64) {
@@ -586,6 +579,7 @@ int dg_set_state(dg_solver *h, const double *u, int64_t count)
 int dg_set_state_device(dg_solver *h, const void *u_dev, int64_t count)
 {
     if (!h || !u_dev) return fail(DG_EINVAL, "NULL argument");
+    if (h->batch) return fail(DG_ESTATE, "solver belongs to a batch");
     int rc = check_count(h, count);
     if (rc || (rc = select_device(h))) return rc;
     if (h->prec == DG_FP64) {
@@ -606,12 +600,13 @@ int dg_step(dg_solver *h, int rk, double dt, int64_t nsteps)
     if (!std::isfinite(dt) || !(dt > 0.0)) return fail(DG_EINVAL, "dt must be finite and > 0");
     if (nsteps < 0) return fail(DG_EINVAL, "nsteps must be >= 0");
     if (!h->has_state) return fail(DG_ESTATE, "dg_set_state has not been called");
+    if (h->batch) return fail(DG_ESTATE, "solver belongs to a batch (use dg_batch_run)");
     if (nsteps == 0) return DG_OK;
     int rc = select_device(h);
     if (rc) return rc;
     if (rk == DG_RK6 && (rc = ensure_rk6(h))) return rc;
     for (int64_t s = 0; s < nsteps; ++s) {
-        rc = rk == DG_RK4 ? step_rk4(h, dt) : rk == DG_RK3 ? step_rk3(h, dt) : step_rk6(h, dt);
+        rc = rk == DG_RK6 ? step_rk6(h, dt) : step_rk34(h, rk, dt);
         if (rc) return rc;
     }
     return DG_OK;

@@ -1,0 +1,380 @@
+// dg_batch.cpp -- batched stepping: many solvers advanced together, one
+// launch per RK stage per kernel class (precision, equation, dim, N, scheme).
+//
+// Per class the batch keeps, on the device: the StageParams of every active
+// member for every stage of its scheme (built by the same stage programs as
+// dg_step, so a member's arithmetic is exactly what dg_step would run), and a
+// virtual-tile -> member map. A tick is one RK step of every active member;
+// dg_batch_run enqueues as many ticks as the shortest remaining member allows,
+// optionally replaying a hipGraph of one tick. Descriptors are rebuilt only
+// when the set of active members changes.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <tuple>
+#include <vector>
+
+#include "dg_host.hpp"
+
+using namespace dg;
+
+namespace {
+
+// A graph of one tick is captured (once per membership) only for runs of at
+// least this many ticks; shorter runs launch directly, since capture and
+// instantiation cost more than a few direct launches.
+constexpr int64_t kGraphMinTicks = 4;
+
+struct Member {
+    dg_solver *h;
+    int rk;
+    double dt;
+    int64_t remaining;
+};
+
+struct Group {
+    int prec = 0, eq = 0, dim = 0, N = 0, rk = 0, stages = 0;
+    BatchFn fn = nullptr;
+    bool buf = true;
+    std::vector<int> idx;          // member indices
+    uint32_t ntiles = 0;
+    size_t off_params = 0, off_solve = 0, off_base = 0;
+    const void *D = nullptr;
+    const uint32_t *ftab = nullptr;
+    int64_t grid = 0;
+};
+
+}  // namespace
+
+struct dg_batch {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int flags = 0;
+    std::vector<Member> members;
+    std::vector<Group> groups;
+    bool dirty = true;
+    char *dbuf = nullptr;
+    size_t dbuf_cap = 0;
+    std::vector<char> staging;
+    hipEvent_t done = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+};
+
+namespace {
+
+int member_index(const dg_batch *b, const dg_solver *h)
+{
+    for (size_t i = 0; i < b->members.size(); ++i)
+        if (b->members[i].h == h) return (int)i;
+    return -1;
+}
+
+void drop_graph(dg_batch *b)
+{
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->gexec = nullptr;
+    b->graph = nullptr;
+}
+
+// Group the active members by class and upload their stage descriptors.
+int rebuild(dg_batch *b)
+{
+    drop_graph(b);
+    b->groups.clear();
+    std::map<std::tuple<int, int, int, int, int>, int> key;
+    for (size_t i = 0; i < b->members.size(); ++i) {
+        const Member &m = b->members[i];
+        if (m.remaining <= 0) continue;
+        const dg_solver *h = m.h;
+        auto k = std::make_tuple(h->prec, h->eq, h->dim, h->N, m.rk);
+        auto it = key.find(k);
+        if (it == key.end()) {
+            Group g;
+            g.prec = h->prec; g.eq = h->eq; g.dim = h->dim; g.N = h->N; g.rk = m.rk;
+            g.stages = stage_count(m.rk);
+            g.fn = batch_fn(h->prec, h->eq, h->dim, h->N);
+            if (!g.fn) return fail(DG_ENOTSUP, "no batched kernel for this class");
+            g.D = h->Dtab;
+            g.ftab = h->ftab;
+            key[k] = (int)b->groups.size();
+            b->groups.push_back(g);
+            it = key.find(k);
+        }
+        b->groups[it->second].idx.push_back((int)i);
+    }
+    // device layout per group [params: stages x n][tile_solve: ntiles][tile_base: n+1];
+    // the host stages params and tile_base, a fill kernel writes tile_solve.
+    // header: per group params and tile_base (staged on the host, one copy);
+    // after it the tile_solve arrays (written on the device).
+    size_t header = 0;
+    for (Group &g : b->groups) {
+        const size_t n = g.idx.size();
+        uint64_t tiles = 0;
+        for (int i : g.idx) {
+            const dg_solver *h = b->members[i].h;
+            tiles += (uint64_t)h->ntiles;
+            const int64_t bytes = h->nodes * h->nvar * (h->prec == DG_FP64 ? 8 : 4);
+            if (bytes >= (int64_t(1) << 31)) g.buf = false;
+        }
+        if (tiles >= (uint64_t(1) << 32)) return fail(DG_ENOTSUP, "batch too large for one launch");
+        g.ntiles = (uint32_t)tiles;
+        g.off_params = header;
+        header = round_up(header + sizeof(StageParams) * n * g.stages);
+        g.off_base = header;
+        header = round_up(header + sizeof(uint32_t) * (n + 1));
+        g.grid = std::min<int64_t>((int64_t)tiles, kMaxGrid);
+    }
+    if (header == 0) return DG_OK;
+    size_t total = header;
+    for (Group &g : b->groups) {
+        g.off_solve = total;
+        total = round_up(total + sizeof(uint32_t) * g.ntiles);
+    }
+    b->staging.resize(header);
+    for (Group &g : b->groups) {
+        const size_t n = g.idx.size();
+        StageParams *par = reinterpret_cast<StageParams *>(b->staging.data() + g.off_params);
+        uint32_t *base = reinterpret_cast<uint32_t *>(b->staging.data() + g.off_base);
+        uint32_t t0 = 0;
+        for (size_t j = 0; j < n; ++j) {
+            const Member &m = b->members[g.idx[j]];
+            for (int s = 0; s < g.stages; ++s) par[s * n + j] = stage_program(m.h, m.rk, s, m.dt);
+            base[j] = t0;
+            t0 += (uint32_t)m.h->ntiles;
+        }
+        base[n] = t0;
+    }
+    if (total > b->dbuf_cap) {
+        DG_HIP(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+        if (b->dbuf) (void)hipFree(b->dbuf);
+        total = std::max(total, 2 * b->dbuf_cap);     // grow geometrically
+        b->dbuf = nullptr;
+        b->dbuf_cap = 0;
+        hipError_t e = hipMalloc((void **)&b->dbuf, total);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            b->dbuf = nullptr;
+            return fail(DG_ENOMEM, "cannot allocate batch descriptors");
+        }
+        b->dbuf_cap = total;
+    }
+    DG_HIP(hipMemcpyAsync(b->dbuf, b->staging.data(), header, hipMemcpyHostToDevice, b->stream),
+           "hipMemcpyAsync");
+    for (const Group &g : b->groups)
+        DG_HIP(launch_fill_tile_map(reinterpret_cast<const uint32_t *>(b->dbuf + g.off_base),
+                                    (uint32_t)g.idx.size(),
+                                    reinterpret_cast<uint32_t *>(b->dbuf + g.off_solve), b->stream),
+               "tile map launch");
+    // the staging buffer is reused by the next rebuild
+    DG_HIP(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    return DG_OK;
+}
+
+int launch_tick(dg_batch *b)
+{
+    int smax = 0;
+    for (const Group &g : b->groups) smax = std::max(smax, g.stages);
+    for (int s = 0; s < smax; ++s)
+        for (const Group &g : b->groups) {
+            if (s >= g.stages) continue;
+            const uint32_t n = (uint32_t)g.idx.size();
+            BatchLaunch L;
+            L.params = reinterpret_cast<const StageParams *>(b->dbuf + g.off_params) + (size_t)s * n;
+            L.tile_solve = reinterpret_cast<const uint32_t *>(b->dbuf + g.off_solve);
+            L.tile_base = reinterpret_cast<const uint32_t *>(b->dbuf + g.off_base);
+            L.D = g.D;
+            L.ftab = g.ftab;
+            L.ntiles = g.ntiles;
+            L.xq = g.ntiles / kXcds;
+            L.xr = g.ntiles % kXcds;
+            L.nsolves = n;
+            DG_HIP(g.fn(L, g.buf, g.grid, b->stream), "batched stage kernel launch");
+        }
+    return DG_OK;
+}
+
+// Member streams wait for the batch work enqueued so far.
+int publish(dg_batch *b)
+{
+    DG_HIP(hipEventRecord(b->done, b->stream), "hipEventRecord");
+    for (const Member &m : b->members)
+        if (m.h->stream != b->stream) DG_HIP(hipStreamWaitEvent(m.h->stream, b->done, 0), "hipStreamWaitEvent");
+    return DG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dg_batch_create(void *hip_stream, int flags, dg_batch **out)
+{
+    if (!out) return fail(DG_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (flags & ~DG_BATCH_GRAPH) return fail(DG_EINVAL, "unknown batch flags");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        return fail(DG_EDEVICE, "no HIP device available");
+    }
+    dg_batch *b = new (std::nothrow) dg_batch();
+    if (!b) return fail(DG_ENOMEM, "host allocation failed");
+    b->flags = flags;
+    hipError_t e = hipGetDevice(&b->device);
+    if (e == hipSuccess) {
+        if (hip_stream) {
+            b->stream = static_cast<hipStream_t>(hip_stream);
+        } else {
+            e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+            b->own_stream = e == hipSuccess;
+        }
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        if (b->own_stream) (void)hipStreamDestroy(b->stream);
+        delete b;
+        return hip_fail(e, "batch setup");
+    }
+    *out = b;
+    return DG_OK;
+}
+
+int dg_batch_destroy(dg_batch *b)
+{
+    if (!b) return DG_OK;
+    (void)hipSetDevice(b->device);
+    (void)hipStreamSynchronize(b->stream);
+    for (Member &m : b->members) m.h->batch = nullptr;
+    drop_graph(b);
+    if (b->dbuf) (void)hipFree(b->dbuf);
+    if (b->done) (void)hipEventDestroy(b->done);
+    if (b->own_stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+    return DG_OK;
+}
+
+int dg_batch_add(dg_batch *b, dg_solver *h, int rk, double dt, int64_t nsteps)
+{
+    if (!b || !h) return fail(DG_EINVAL, "NULL argument");
+    if (rk == DG_RK6) return fail(DG_ENOTSUP, "batched stepping supports DG_RK3 and DG_RK4");
+    if (rk != DG_RK3 && rk != DG_RK4) return fail(DG_EINVAL, "rk must be 3 or 4");
+    if (!std::isfinite(dt) || !(dt > 0.0)) return fail(DG_EINVAL, "dt must be finite and > 0");
+    if (nsteps < 1) return fail(DG_EINVAL, "nsteps must be >= 1");
+    if (!h->has_state) return fail(DG_ESTATE, "dg_set_state has not been called");
+    if (h->batch) return fail(DG_ESTATE, "solver already belongs to a batch");
+    if (h->device != b->device) return fail(DG_EINVAL, "solver is on another device");
+    int rc = select_device(h);
+    if (rc) return rc;
+    // the batch's work on h follows everything already enqueued on h's stream
+    if (h->stream != b->stream) {
+        hipEvent_t ev;
+        DG_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "hipEventCreate");
+        hipError_t e = hipEventRecord(ev, h->stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, ev, 0);
+        (void)hipEventDestroy(ev);
+        if (e != hipSuccess) return hip_fail(e, "stream ordering");
+    }
+    b->members.push_back(Member{h, rk, dt, nsteps});
+    h->batch = b;
+    b->dirty = true;
+    return DG_OK;
+}
+
+int dg_batch_remove(dg_batch *b, dg_solver *h)
+{
+    if (!b || !h) return fail(DG_EINVAL, "NULL argument");
+    const int i = member_index(b, h);
+    if (i < 0) return fail(DG_EINVAL, "solver is not a member of this batch");
+    int rc = publish(b);
+    if (rc) return rc;
+    const bool active = b->members[i].remaining > 0;
+    b->members.erase(b->members.begin() + i);
+    h->batch = nullptr;
+    if (active) b->dirty = true;
+    return DG_OK;
+}
+
+int dg_batch_run(dg_batch *b, int64_t max_steps, int64_t *steps_done)
+{
+    if (!b) return fail(DG_EINVAL, "batch is NULL");
+    if (max_steps < 0) return fail(DG_EINVAL, "max_steps must be >= 0");
+    if (steps_done) *steps_done = 0;
+    DG_HIP(hipSetDevice(b->device), "hipSetDevice");
+    int64_t steps = max_steps;
+    bool any = false;
+    for (const Member &m : b->members)
+        if (m.remaining > 0) {
+            steps = std::min(steps, m.remaining);
+            any = true;
+        }
+    if (!any || steps == 0) return DG_OK;
+    int rc;
+    if (b->dirty) {
+        if ((rc = rebuild(b))) return rc;
+        b->dirty = false;
+    }
+    if ((b->flags & DG_BATCH_GRAPH) && (b->gexec || steps >= kGraphMinTicks)) {
+        if (!b->gexec) {
+            DG_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+            rc = launch_tick(b);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(b->stream, &g);
+            if (rc) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+            if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+            b->graph = g;
+            e = hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                drop_graph(b);
+                return hip_fail(e, "hipGraphInstantiate");
+            }
+        }
+        for (int64_t t = 0; t < steps; ++t) DG_HIP(hipGraphLaunch(b->gexec, b->stream), "hipGraphLaunch");
+    } else {
+        for (int64_t t = 0; t < steps; ++t)
+            if ((rc = launch_tick(b))) return rc;
+    }
+    for (Member &m : b->members)
+        if (m.remaining > 0) {
+            m.remaining -= steps;
+            if (m.remaining == 0) b->dirty = true;
+        }
+    if ((rc = publish(b))) return rc;
+    if (steps_done) *steps_done = steps;
+    return DG_OK;
+}
+
+int dg_batch_remaining(const dg_batch *b, const dg_solver *h, int64_t *remaining)
+{
+    if (!b || !h || !remaining) return fail(DG_EINVAL, "NULL argument");
+    const int i = member_index(b, h);
+    if (i < 0) return fail(DG_EINVAL, "solver is not a member of this batch");
+    *remaining = std::max<int64_t>(b->members[i].remaining, 0);
+    return DG_OK;
+}
+
+int dg_batch_size(const dg_batch *b, int *members, int *active)
+{
+    if (!b) return fail(DG_EINVAL, "batch is NULL");
+    int a = 0;
+    for (const Member &m : b->members) a += m.remaining > 0;
+    if (members) *members = (int)b->members.size();
+    if (active) *active = a;
+    return DG_OK;
+}
+
+int dg_batch_synchronize(dg_batch *b)
+{
+    if (!b) return fail(DG_EINVAL, "batch is NULL");
+    DG_HIP(hipSetDevice(b->device), "hipSetDevice");
+    DG_HIP(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    return DG_OK;
+}
+
+}  // extern "C"

@@ -1,9 +1,19 @@
-// dg_host.hpp -- host-only declarations of the runtime (not part of the ABI).
+// dg_host.hpp -- host-only declarations of the runtime (not part of the ABI):
+// the solver object behind the opaque dg_solver handle, workspace layout,
+// error helpers and the fused-stage programs shared by single-solve stepping
+// and batched stepping.
 #pragma once
 
+#include <string>
+
+#include "../../include/dg.h"
 #include "dg_internal.hpp"
 
 namespace dg {
+
+constexpr size_t kAlign = 256;
+constexpr int64_t kReduceBlocks = 1024;
+constexpr size_t kFaceTableBytes = 16384;
 
 // LGL nodes xi[N+1], weights w[N+1] and D[(N+1)^2] (row-major, D[i*(N+1)+j]).
 void lgl_operator(int N, double *xi, double *w, double *D);
@@ -11,5 +21,63 @@ void lgl_operator(int N, double *xi, double *w, double *D);
 // Face-point descriptor table of a workgroup tile (4 uint32 per face point).
 int face_table_size(int dim, int N, int epb);
 void build_face_table(int dim, int N, int epb, uint32_t *tab);
+
+// Device workspace of one solver: tables, then the RK arrays.
+struct Layout {
+    size_t tables = 0;      // D (state precision), w (FP64), reduction partials, face table
+    size_t array = 0;       // one state array
+    size_t base = 0;        // tables + 4 arrays (RK3/RK4)
+    size_t rk6 = 0;         // base + 5 more arrays (RK6 k-store)
+};
+
+// Record msg as the calling thread's last error and return code.
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+size_t round_up(size_t x);
+
+#define DG_HIP(call, what)                                     \
+    do {                                                       \
+        hipError_t e_ = (call);                                \
+        if (e_ != hipSuccess) return ::dg::hip_fail(e_, what); \
+    } while (0)
+
+}  // namespace dg
+
+struct dg_solver {
+    int dim = 0, N = 0, eq = 0, prec = 0, nvar = 0, n1 = 0, np = 0;
+    int64_t K[3] = {1, 1, 1};
+    int64_t nodes = 0, unknowns = 0;
+    double par[3] = {0, 0, 0};
+    double xi[dg::kMaxNP1], w[dg::kMaxNP1], D[dg::kMaxNP1 * dg::kMaxNP1];
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    bool own_ws = false;
+    dg::Layout lay;
+    void *Dtab = nullptr;
+    double *wtab = nullptr;
+    uint32_t *ftab = nullptr;
+    double *partial = nullptr;
+    void *U = nullptr, *A = nullptr, *Ya = nullptr, *Yb = nullptr;
+    void *kx[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // RK6 k3..k7
+    char *rk6_mem = nullptr;        // library-owned RK6 extension
+    bool has_state = false;
+    dg::StageFn stage = nullptr;
+    int epb = 0;
+    int64_t tiles_x = 0, slab = 1, ntiles = 0, grid = 0;
+    dg_batch *batch = nullptr;      // batch this solver belongs to, if any
+};
+
+namespace dg {
+
+int select_device(const dg_solver *h);
+// Launch parameters common to every stage of h (mesh, operator, tiles).
+StageParams base_params(const dg_solver *h);
+// Number of fused stages of scheme rk (3, 4 or 7 for RK6).
+int stage_count(int rk);
+// Parameters of fused stage s of the RK3/RK4 schedule with step dt.
+StageParams stage_program(const dg_solver *h, int rk, int s, double dt);
 
 }  // namespace dg

@@ -3,4 +3,5 @@
 
 namespace dg {
 StageFn stage_fn_f32_d3_euler(int N) { return pick_stage_n<float, 3, 1>(N); }
+BatchFn batch_fn_f32_d3_euler(int N) { return pick_batch_n<float, 3, 1>(N); }
 }  // namespace dg

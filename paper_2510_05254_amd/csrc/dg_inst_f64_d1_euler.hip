@@ -3,4 +3,5 @@
 
 namespace dg {
 StageFn stage_fn_f64_d1_euler(int N) { return pick_stage_n<double, 1, 1>(N); }
+BatchFn batch_fn_f64_d1_euler(int N) { return pick_batch_n<double, 1, 1>(N); }
 }  // namespace dg

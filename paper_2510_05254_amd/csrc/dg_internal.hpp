@@ -69,6 +69,16 @@ struct StageParams {
     const uint32_t *ftab;  // face-point descriptors of a tile (dg_tables.cpp)
 };
 
+// One batched stage launch over the solves of one kernel class.
+struct BatchLaunch {
+    const StageParams *params;   // per solve, this stage's parameters (device)
+    const uint32_t *tile_solve;  // solve owning each virtual tile (device)
+    const uint32_t *tile_base;   // first virtual tile of each solve (device)
+    const void *D;               // differentiation matrix of the class (device)
+    const uint32_t *ftab;        // face-point table of the class (device)
+    uint32_t ntiles, xq, xr, nsolves;
+};
+
 // Elementwise linear combination (RK6 stage assembly):
 //   out = a_base * base + (sum_j c[j] * src[j]) * scale
 struct CombineParams {
@@ -104,9 +114,11 @@ struct CastParams {
 };
 
 typedef hipError_t (*StageFn)(const StageParams &p, int64_t grid, hipStream_t s);
+typedef hipError_t (*BatchFn)(const BatchLaunch &b, bool buf, int64_t grid, hipStream_t s);
 
 // Stage launcher for (precision, equation, dim, N); nullptr if not built.
 StageFn stage_fn(int precision, int equation, int dim, int N);
+BatchFn batch_fn(int precision, int equation, int dim, int N);
 // Threads per block and elements per block of the stage kernel for (dim, N).
 int stage_threads(int dim, int N);
 int stage_epb(int dim, int N);
@@ -114,6 +126,10 @@ int stage_epb(int dim, int N);
 hipError_t launch_combine(int precision, const CombineParams &p, hipStream_t s);
 hipError_t launch_reduce(int precision, const ReduceParams &p, int64_t blocks, hipStream_t s);
 hipError_t launch_cast(int to_precision, int from_precision, const CastParams &p, hipStream_t s);
+// tile_solve[t] = j for tile_base[j] <= t < tile_base[j+1], j < nsolves
+// (tile_base holds nsolves + 1 entries, the last one the total tile count).
+hipError_t launch_fill_tile_map(const uint32_t *tile_base, uint32_t nsolves, uint32_t *tile_solve,
+                                hipStream_t s);
 constexpr int kReduceThreads = 256;
 
 }  // namespace dg

@@ -18,6 +18,34 @@ StageFn stage_fn_f32_d2_euler(int N);
 StageFn stage_fn_f32_d3_adv(int N);
 StageFn stage_fn_f32_d3_euler(int N);
 
+BatchFn batch_fn_f64_d1_adv(int N);
+BatchFn batch_fn_f64_d1_euler(int N);
+BatchFn batch_fn_f64_d2_adv(int N);
+BatchFn batch_fn_f64_d2_euler(int N);
+BatchFn batch_fn_f64_d3_adv(int N);
+BatchFn batch_fn_f64_d3_euler(int N);
+BatchFn batch_fn_f32_d1_adv(int N);
+BatchFn batch_fn_f32_d1_euler(int N);
+BatchFn batch_fn_f32_d2_adv(int N);
+BatchFn batch_fn_f32_d2_euler(int N);
+BatchFn batch_fn_f32_d3_adv(int N);
+BatchFn batch_fn_f32_d3_euler(int N);
+
+BatchFn batch_fn(int precision, int equation, int dim, int N)
+{
+    typedef BatchFn (*Pick)(int);
+    static const Pick table[2][3][2] = {
+        {{batch_fn_f64_d1_adv, batch_fn_f64_d1_euler},
+         {batch_fn_f64_d2_adv, batch_fn_f64_d2_euler},
+         {batch_fn_f64_d3_adv, batch_fn_f64_d3_euler}},
+        {{batch_fn_f32_d1_adv, batch_fn_f32_d1_euler},
+         {batch_fn_f32_d2_adv, batch_fn_f32_d2_euler},
+         {batch_fn_f32_d3_adv, batch_fn_f32_d3_euler}}};
+    if (precision < 0 || precision > 1 || equation < 0 || equation > 1 || dim < 1 || dim > 3)
+        return nullptr;
+    return table[precision][dim - 1][equation](N);
+}
+
 StageFn stage_fn(int precision, int equation, int dim, int N)
 {
     typedef StageFn (*Pick)(int);
@@ -162,6 +190,24 @@ hipError_t launch_cast(int to_precision, int from_precision, const CastParams &p
         hipLaunchKernelGGL((cast_kernel<double, float>), dim3((unsigned)g), dim3(256), 0, s, p);
     else
         return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched-launch tile map: one workgroup per solve writes its tile range.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) fill_tile_map_kernel(const uint32_t *base, uint32_t *solve)
+{
+    const uint32_t j = blockIdx.x;
+    const uint32_t lo = base[j], hi = base[j + 1];
+    for (uint32_t t = lo + threadIdx.x; t < hi; t += blockDim.x) solve[t] = j;
+}
+
+hipError_t launch_fill_tile_map(const uint32_t *tile_base, uint32_t nsolves, uint32_t *tile_solve,
+                                hipStream_t s)
+{
+    if (nsolves == 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_tile_map_kernel, dim3(nsolves), dim3(256), 0, s, tile_base, tile_solve);
     return hipGetLastError();
 }
 

@@ -197,23 +197,64 @@ struct Arr<real, false> {
     }
 };
 
-template <typename real, int DIM, int N, int EQ, bool BUF, int SPOL = 0, int YPOL = 0, int TM = 1>
-__global__ void __launch_bounds__((Geo<DIM, N, TM>::THREADS)) __attribute__((amdgpu_waves_per_eu(4)))
-stage_kernel(const StageParams p)
+// LDS of one stage-kernel workgroup
+template <typename real, int DIM, int N, int EQ, int TM>
+struct StageLds {
+    using G = Geo<DIM, N, TM>;
+    static constexpr int NV = Vars<EQ, DIM>::NV, NSYM = Vars<EQ, DIM>::NSYM;
+    real sY[NV][G::TN];
+    real sP[NSYM > 0 ? NSYM : 1][EQ == 1 ? G::TN : 1];
+    real sRi[EQ == 1 ? G::TN : 1];
+    real sL[NV][G::NL];
+    real sD[G::N1 * G::N1];
+};
+
+// per-thread constants of a workgroup (independent of the tile)
+template <int DIM, int N, int TM>
+struct ThreadSetup {
+    int tid, slot, n, ijk[3];
+    uint32_t fw0, fw1, fw2, fw3;    // this thread's first face point
+    __device__ __forceinline__ ThreadSetup(const uint32_t *ftab)
+    {
+        using G = Geo<DIM, N, TM>;
+        tid = threadIdx.x;
+        slot = tid / G::NP;
+        n = tid - slot * G::NP;
+        ijk[0] = n % G::N1;
+        ijk[1] = DIM > 1 ? (n / G::N1) % G::N1 : 0;
+        ijk[2] = DIM > 2 ? n / (G::N1 * G::N1) : 0;
+        fw0 = fw1 = fw2 = fw3 = 0;
+        if (tid < G::NF) {
+            fw0 = ftab[4 * tid + 0];
+            fw1 = ftab[4 * tid + 1];
+            fw2 = ftab[4 * tid + 2];
+            fw3 = ftab[4 * tid + 3];
+        }
+    }
+};
+
+// One tile (EPB consecutive elements along x) of one RHS + RK stage: tile L of
+// the solve described by p, in that solve's tile numbering.
+template <typename real, int DIM, int N, int EQ, bool BUF, int SPOL, int YPOL, int TM>
+__device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
+                                           StageLds<real, DIM, N, EQ, TM> &lds,
+                                           const ThreadSetup<DIM, N, TM> &ts)
 {
     using G = Geo<DIM, N, TM>;
-    constexpr int N1 = G::N1, NP = G::NP, NF1 = G::NF1, EPB = G::EPB, TN = G::TN;
-    constexpr int THREADS = G::THREADS, NF = G::NF, NL = G::NL;
-    constexpr int NV = Vars<EQ, DIM>::NV, NSYM = Vars<EQ, DIM>::NSYM;
+    constexpr int N1 = G::N1, NP = G::NP, NF1 = G::NF1, EPB = G::EPB;
+    constexpr int THREADS = G::THREADS, NF = G::NF;
+    constexpr int NV = Vars<EQ, DIM>::NV;
     constexpr real INVW0 = real(N * (N + 1)) / real(2);     // 1/w_0 = 1/w_N
     using A = Arr<real, BUF>;
     using idx_t = typename A::idx_t;
-
-    __shared__ real sY[NV][TN];
-    __shared__ real sP[NSYM > 0 ? NSYM : 1][EQ == 1 ? TN : 1];
-    __shared__ real sRi[EQ == 1 ? TN : 1];
-    __shared__ real sL[NV][NL];
-    __shared__ real sD[N1 * N1];
+    auto &sY = lds.sY;
+    auto &sP = lds.sP;
+    auto &sRi = lds.sRi;
+    auto &sL = lds.sL;
+    auto &sD = lds.sD;
+    const int tid = ts.tid, slot = ts.slot, n = ts.n;
+    const int *ijk = ts.ijk;
+    const uint32_t fw0 = ts.fw0, fw1 = ts.fw1, fw2 = ts.fw2, fw3 = ts.fw3;
 
     const A yin(p.yin, p.stride, NV);
     real par[3], rdx2[3];
@@ -225,245 +266,259 @@ stage_kernel(const StageParams p)
     const real c2 = par[0] * par[0];
     const int64_t K0 = p.K[0], K1 = p.K[1], K2 = p.K[2];
 
-    const int tid = threadIdx.x;
-    if (tid < N1 * N1) sD[tid] = static_cast<const real *>(p.D)[tid];
-    const int slot = tid / NP;
-    const int n = tid - slot * NP;
-    int ijk[3];
-    ijk[0] = n % N1;
-    ijk[1] = DIM > 1 ? (n / N1) % N1 : 0;
-    ijk[2] = DIM > 2 ? n / (N1 * N1) : 0;
+    int64_t tx, ey, ez;
+    if constexpr (DIM == 1) {
+        tx = L; ey = 0; ez = 0;
+    } else if constexpr (DIM == 2) {
+        const uint32_t r1 = fast_div(L, p.fd_tx);
+        tx = L - r1 * p.fd_tx.div; ey = r1; ez = 0;
+    } else {
+        const uint32_t r1 = fast_div(L, p.fd_tx);
+        const uint32_t r2 = fast_div(r1, p.fd_slab);
+        const uint32_t r3 = fast_div(r2, p.fd_k1);
+        tx = L - r1 * p.fd_tx.div;
+        const uint32_t zs = r1 - r2 * p.fd_slab.div;
+        ey = r2 - r3 * p.fd_k1.div;
+        ez = int64_t(r3) * p.fd_slab.div + zs;
+    }
+    const int64_t ex0 = tx * EPB;
+    const int nact = (int)((K0 - ex0) < EPB ? (K0 - ex0) : EPB);
+    const int64_t ebase = K0 * (ey + K1 * ez);     // element index of (0, ey, ez)
 
-    // this thread's first face point (tile independent)
-    uint32_t fw0 = 0, fw1 = 0, fw2 = 0, fw3 = 0;
-    if (tid < NF) {
-        fw0 = p.ftab[4 * tid + 0];
-        fw1 = p.ftab[4 * tid + 1];
-        fw2 = p.ftab[4 * tid + 2];
-        fw3 = p.ftab[4 * tid + 3];
+    // Face point fields (see dg_tables.cpp): w0 = d | own_slot << 2 |
+    // (other_slot+1) << 10 | other_is_lower << 18 | kind << 19,
+    // w1 = own_node | other_node << 16, w2 = plane or slot, w3 = lift slots.
+    auto face_valid = [&](uint32_t w0, uint32_t ps) {
+        return ((w0 >> 19) & 3u) == 0 ? ps <= uint32_t(nact) : ps < uint32_t(nact);
+    };
+    auto other_outside = [&](uint32_t w0, uint32_t ps) {
+        return ((w0 >> 10) & 0xffu) == 0 || (((w0 >> 19) & 3u) == 0 && ps == uint32_t(nact));
+    };
+    // element holding the other side when it lies outside the tile
+    auto outside_elem = [&](uint32_t w0, uint32_t ps) -> int64_t {
+        const int d = int(w0 & 3u), kind = int((w0 >> 19) & 3u);
+        if (kind == 0) {
+            int64_t ex = ((w0 >> 18) & 1u) ? ex0 - 1 : ex0 + nact;
+            if (ex < 0) ex += K0;
+            if (ex >= K0) ex -= K0;
+            return ebase + ex;
+        }
+        int64_t yy = ey, zz = ez;
+        const int step = kind == 2 ? 1 : -1;
+        if (d == 1) {
+            yy += step;
+            if (yy < 0) yy += K1;
+            if (yy >= K1) yy -= K1;
+        } else {
+            zz += step;
+            if (zz < 0) zz += K2;
+            if (zz >= K2) zz -= K2;
+        }
+        return ex0 + int64_t(ps) + K0 * (yy + K1 * zz);
+    };
+
+    // ---- prefetch the outside state of this thread's first face point
+    real g[NV];
+    if (tid < NF && face_valid(fw0, fw2) && other_outside(fw0, fw2)) {
+        const idx_t gn = idx_t(outside_elem(fw0, fw2) * NP + (fw1 >> 16));
+#pragma unroll
+        for (int v = 0; v < NV; ++v) g[v] = yin.ld(v, gn);
     }
 
-    for (uint32_t vb = blockIdx.x; vb < p.ntiles32; vb += gridDim.x) {
-        // ---- tile coordinates (XCD-contiguous numbering, magic divisions)
-        const uint32_t xb = vb & (kXcds - 1), jb = vb / kXcds;
-        const uint32_t L = p.plain_order ? vb : xb * p.xq + (xb < p.xr ? xb : p.xr) + jb;
-        int64_t tx, ey, ez;
-        if constexpr (DIM == 1) {
-            tx = L; ey = 0; ez = 0;
-        } else if constexpr (DIM == 2) {
-            const uint32_t r1 = fast_div(L, p.fd_tx);
-            tx = L - r1 * p.fd_tx.div; ey = r1; ez = 0;
-        } else {
-            const uint32_t r1 = fast_div(L, p.fd_tx);
-            const uint32_t r2 = fast_div(r1, p.fd_slab);
-            const uint32_t r3 = fast_div(r2, p.fd_k1);
-            tx = L - r1 * p.fd_tx.div;
-            const uint32_t zs = r1 - r2 * p.fd_slab.div;
-            ey = r2 - r3 * p.fd_k1.div;
-            ez = int64_t(r3) * p.fd_slab.div + zs;
+    // ---- phase 1: state, 1/rho and flux tensor into LDS
+    const bool active = slot < nact;
+    const int ln = slot * NP + n;
+    const idx_t gi = idx_t((ebase + ex0 + slot) * NP + n);
+    real y[NV];
+    if (active) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) y[v] = yin.template ld<YPOL>(v, gi);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sY[v][ln] = y[v];
+        if constexpr (EQ == 1) {
+            const real rinv = recip(y[0]);
+            sRi[ln] = rinv;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a)
+#pragma unroll
+                for (int b = a; b < DIM; ++b)
+                    sP[sym_index(a, b, DIM)][ln] = sym_flux(y[1 + a], y[1 + b], y[0], rinv, c2, a == b);
         }
-        const int64_t ex0 = tx * EPB;
-        const int nact = (int)((K0 - ex0) < EPB ? (K0 - ex0) : EPB);
-        const int64_t ebase = K0 * (ey + K1 * ez);     // element index of (0, ey, ez)
+    }
+    __syncthreads();
 
-        // Face point fields (see dg_tables.cpp): w0 = d | own_slot << 2 |
-        // (other_slot+1) << 10 | other_is_lower << 18 | kind << 19,
-        // w1 = own_node | other_node << 16, w2 = plane or slot, w3 = lift slots.
-        auto face_valid = [&](uint32_t w0, uint32_t ps) {
-            return ((w0 >> 19) & 3u) == 0 ? ps <= uint32_t(nact) : ps < uint32_t(nact);
-        };
-        auto other_outside = [&](uint32_t w0, uint32_t ps) {
-            return ((w0 >> 10) & 0xffu) == 0 || (((w0 >> 19) & 3u) == 0 && ps == uint32_t(nact));
-        };
-        // element holding the other side when it lies outside the tile
-        auto outside_elem = [&](uint32_t w0, uint32_t ps) -> int64_t {
-            const int d = int(w0 & 3u), kind = int((w0 >> 19) & 3u);
-            if (kind == 0) {
-                int64_t ex = ((w0 >> 18) & 1u) ? ex0 - 1 : ex0 + nact;
-                if (ex < 0) ex += K0;
-                if (ex >= K0) ex -= K0;
-                return ebase + ex;
-            }
-            int64_t yy = ey, zz = ez;
-            const int step = kind == 2 ? 1 : -1;
-            if (d == 1) {
-                yy += step;
-                if (yy < 0) yy += K1;
-                if (yy >= K1) yy -= K1;
-            } else {
-                zz += step;
-                if (zz < 0) zz += K2;
-                if (zz >= K2) zz -= K2;
-            }
-            return ex0 + int64_t(ps) + K0 * (yy + K1 * zz);
-        };
-
-        // ---- prefetch the outside state of this thread's first face point
-        real g[NV];
-        if (tid < NF && face_valid(fw0, fw2) && other_outside(fw0, fw2)) {
-            const idx_t gn = idx_t(outside_elem(fw0, fw2) * NP + (fw1 >> 16));
+    // ---- phase 2: Lax-Friedrichs flux at the tile's face points, lifts to LDS.
+    // With sigma = -1 when the other side is the lower one,
+    //   Fhat = 1/2 [(F_own + F_oth) - (sigma alpha)(U_oth - U_own)]
+    // is eq. LF with (U^-, U^+) = (lower, upper); two tiles sharing a face
+    // evaluate it with the roles swapped and get the same bits (the sum
+    // commutes and both factors of the product change sign exactly).
+    for (int f = tid; f < NF; f += THREADS) {
+        uint32_t w0 = fw0, w1 = fw1, w2 = fw2, w3 = fw3;
+        if (f >= THREADS) {
+            w0 = p.ftab[4 * f + 0];
+            w1 = p.ftab[4 * f + 1];
+            w2 = p.ftab[4 * f + 2];
+            w3 = p.ftab[4 * f + 3];
+        }
+        if (!face_valid(w0, w2)) continue;
+        const bool oglob = other_outside(w0, w2);
+        if (f >= THREADS && oglob) {
+            const idx_t gn = idx_t(outside_elem(w0, w2) * NP + (w1 >> 16));
 #pragma unroll
             for (int v = 0; v < NV; ++v) g[v] = yin.ld(v, gn);
         }
-
-        // ---- phase 1: state, 1/rho and flux tensor into LDS
-        const bool active = slot < nact;
-        const int ln = slot * NP + n;
-        const idx_t gi = idx_t((ebase + ex0 + slot) * NP + n);
-        real y[NV];
-        if (active) {
+        const int own_q = int((w0 >> 2) & 0xffu) * NP + int(w1 & 0xffffu);
+        const int oth_q = (int((w0 >> 10) & 0xffu) - 1) * NP + int(w1 >> 16);
+        const bool oth_lower = (w0 >> 18) & 1u;
+        const int own_l = int(w3 & 0xffffu), oth_l = int(w3 >> 16);
+        auto face = [&](auto dconst) {
+            constexpr int D = decltype(dconst)::value;
+            real Uo[NV], Fo[NV], Ut[NV], Ft[NV], lo, lt;
+            auto from_lds = [&](int q, real *U, real *F, real &lam) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) y[v] = yin.template ld<YPOL>(v, gi);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) sY[v][ln] = y[v];
-            if constexpr (EQ == 1) {
-                const real rinv = recip(y[0]);
-                sRi[ln] = rinv;
-#pragma unroll
-                for (int a = 0; a < DIM; ++a)
-#pragma unroll
-                    for (int b = a; b < DIM; ++b)
-                        sP[sym_index(a, b, DIM)][ln] = sym_flux(y[1 + a], y[1 + b], y[0], rinv, c2, a == b);
-            }
-        }
-        __syncthreads();
-
-        // ---- phase 2: Lax-Friedrichs flux at the tile's face points, lifts to LDS.
-        // With sigma = -1 when the other side is the lower one,
-        //   Fhat = 1/2 [(F_own + F_oth) - (sigma alpha)(U_oth - U_own)]
-        // is eq. LF with (U^-, U^+) = (lower, upper); two tiles sharing a face
-        // evaluate it with the roles swapped and get the same bits (the sum
-        // commutes and both factors of the product change sign exactly).
-        for (int f = tid; f < NF; f += THREADS) {
-            uint32_t w0 = fw0, w1 = fw1, w2 = fw2, w3 = fw3;
-            if (f >= THREADS) {
-                w0 = p.ftab[4 * f + 0];
-                w1 = p.ftab[4 * f + 1];
-                w2 = p.ftab[4 * f + 2];
-                w3 = p.ftab[4 * f + 3];
-            }
-            if (!face_valid(w0, w2)) continue;
-            const bool oglob = other_outside(w0, w2);
-            if (f >= THREADS && oglob) {
-                const idx_t gn = idx_t(outside_elem(w0, w2) * NP + (w1 >> 16));
-#pragma unroll
-                for (int v = 0; v < NV; ++v) g[v] = yin.ld(v, gn);
-            }
-            const int own_q = int((w0 >> 2) & 0xffu) * NP + int(w1 & 0xffffu);
-            const int oth_q = (int((w0 >> 10) & 0xffu) - 1) * NP + int(w1 >> 16);
-            const bool oth_lower = (w0 >> 18) & 1u;
-            const int own_l = int(w3 & 0xffffu), oth_l = int(w3 >> 16);
-            auto face = [&](auto dconst) {
-                constexpr int D = decltype(dconst)::value;
-                real Uo[NV], Fo[NV], Ut[NV], Ft[NV], lo, lt;
-                auto from_lds = [&](int q, real *U, real *F, real &lam) {
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) U[v] = sY[v][q];
-                    if constexpr (EQ == 0) {
+                for (int v = 0; v < NV; ++v) U[v] = sY[v][q];
+                if constexpr (EQ == 0) {
 #pragma clang fp contract(off)
-                        F[0] = par[D] * U[0];
-                        lam = fabs(par[D]);
-                    } else {
-                        F[0] = U[1 + D];
-#pragma unroll
-                        for (int k = 0; k < DIM; ++k) F[1 + k] = sP[sym_index(D, k, DIM)][q];
-                        lam = wave_speed(F[0], sRi[q], par[0]);
-                    }
-                };
-                from_lds(own_q, Uo, Fo, lo);
-                if (oglob) {
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) Ut[v] = g[v];
-                    flux_of<real, DIM, EQ, D>(Ut, par, Ft, lt);
+                    F[0] = par[D] * U[0];
+                    lam = fabs(par[D]);
                 } else {
-                    from_lds(oth_q, Ut, Ft, lt);
-                }
-                const real alpha = lo > lt ? lo : lt;
-                const real sa = oth_lower ? -alpha : alpha;
-                const real sl = rdx2[D] * INVW0;
-                const real so = oth_lower ? sl : -sl;     // lift sign of the own side
+                    F[0] = U[1 + D];
 #pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    const real fh = real(0.5) * ((Fo[v] + Ft[v]) - sa * (Ut[v] - Uo[v]));
-                    sL[v][own_l] = so * (fh - Fo[v]);
-                    if (!oglob) sL[v][oth_l] = -so * (fh - Ft[v]);
+                    for (int k = 0; k < DIM; ++k) F[1 + k] = sP[sym_index(D, k, DIM)][q];
+                    lam = wave_speed(F[0], sRi[q], par[0]);
                 }
             };
-            const int d = int(w0 & 3u);
-            if (d == 0) face(std::integral_constant<int, 0>());
-            if constexpr (DIM > 1) if (d == 1) face(std::integral_constant<int, 1>());
-            if constexpr (DIM > 2) if (d == 2) face(std::integral_constant<int, 2>());
-        }
-        __syncthreads();
+            from_lds(own_q, Uo, Fo, lo);
+            if (oglob) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) Ut[v] = g[v];
+                flux_of<real, DIM, EQ, D>(Ut, par, Ft, lt);
+            } else {
+                from_lds(oth_q, Ut, Ft, lt);
+            }
+            const real alpha = lo > lt ? lo : lt;
+            const real sa = oth_lower ? -alpha : alpha;
+            const real sl = rdx2[D] * INVW0;
+            const real so = oth_lower ? sl : -sl;     // lift sign of the own side
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const real fh = real(0.5) * ((Fo[v] + Ft[v]) - sa * (Ut[v] - Uo[v]));
+                sL[v][own_l] = so * (fh - Fo[v]);
+                if (!oglob) sL[v][oth_l] = -so * (fh - Ft[v]);
+            }
+        };
+        const int d = int(w0 & 3u);
+        if (d == 0) face(std::integral_constant<int, 0>());
+        if constexpr (DIM > 1) if (d == 1) face(std::integral_constant<int, 1>());
+        if constexpr (DIM > 2) if (d == 2) face(std::integral_constant<int, 2>());
+    }
+    __syncthreads();
 
-        // ---- phase 3: volume term + lifts, RK stage combination, store
-        if (active) {
-            real R[NV];
+    // ---- phase 3: volume term + lifts, RK stage combination, store
+    if (active) {
+        real R[NV];
 #pragma unroll
-            for (int v = 0; v < NV; ++v) R[v] = real(0);
-            const int base = slot * NP;
+        for (int v = 0; v < NV; ++v) R[v] = real(0);
+        const int base = slot * NP;
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) {
-                const int id = ijk[d];
-                const int sd = d == 0 ? 1 : (d == 1 ? N1 : N1 * N1);
-                const int line0 = base + n - id * sd;
-                real acc[NV];
+        for (int d = 0; d < DIM; ++d) {
+            const int id = ijk[d];
+            const int sd = d == 0 ? 1 : (d == 1 ? N1 : N1 * N1);
+            const int line0 = base + n - id * sd;
+            real acc[NV];
 #pragma unroll
-                for (int v = 0; v < NV; ++v) acc[v] = real(0);
+            for (int v = 0; v < NV; ++v) acc[v] = real(0);
 #pragma unroll 1
-                for (int m = 0; m < N1; ++m) {
-                    const real dm = sD[id * N1 + m];
-                    const int q = line0 + m * sd;
-                    if constexpr (EQ == 0) {
-                        acc[0] += dm * sY[0][q];
-                    } else {
-                        acc[0] += dm * sY[1 + d][q];
-#pragma unroll
-                        for (int k = 0; k < DIM; ++k) acc[1 + k] += dm * sP[sym_index(d, k, DIM)][q];
-                    }
-                }
+            for (int m = 0; m < N1; ++m) {
+                const real dm = sD[id * N1 + m];
+                const int q = line0 + m * sd;
                 if constexpr (EQ == 0) {
-                    R[0] -= rdx2[d] * (par[d] * acc[0]);
+                    acc[0] += dm * sY[0][q];
                 } else {
+                    acc[0] += dm * sY[1 + d][q];
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) R[v] -= rdx2[d] * acc[v];
-                }
-                if (id == 0 || id == N) {
-                    const int t = d == 0 ? (DIM > 1 ? ijk[1] + N1 * ijk[2] : 0)
-                                         : (d == 1 ? ijk[0] + N1 * ijk[2] : ijk[0] + N1 * ijk[1]);
-                    const int li = ((d * EPB + slot) * 2 + (id == N ? 1 : 0)) * NF1 + t;
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) R[v] += sL[v][li];
+                    for (int k = 0; k < DIM; ++k) acc[1 + k] += dm * sP[sym_index(d, k, DIM)][q];
                 }
             }
-            real a0[NV], a1[NV];
-            if (p.nin > 0) {
-                const A in0(p.in0, p.stride, NV);
+            if constexpr (EQ == 0) {
+                R[0] -= rdx2[d] * (par[d] * acc[0]);
+            } else {
 #pragma unroll
-                for (int v = 0; v < NV; ++v) a0[v] = in0.template ld<SPOL>(v, gi);
+                for (int v = 0; v < NV; ++v) R[v] -= rdx2[d] * acc[v];
             }
-            if (p.nin > 1) {
-                const A in1(p.in1, p.stride, NV);
+            if (id == 0 || id == N) {
+                const int t = d == 0 ? (DIM > 1 ? ijk[1] + N1 * ijk[2] : 0)
+                                     : (d == 1 ? ijk[0] + N1 * ijk[2] : ijk[0] + N1 * ijk[1]);
+                const int li = ((d * EPB + slot) * 2 + (id == N ? 1 : 0)) * NF1 + t;
 #pragma unroll
-                for (int v = 0; v < NV; ++v) a1[v] = in1.template ld<SPOL>(v, gi);
+                for (int v = 0; v < NV; ++v) R[v] += sL[v][li];
             }
+        }
+        real a0[NV], a1[NV];
+        if (p.nin > 0) {
+            const A in0(p.in0, p.stride, NV);
 #pragma unroll
-            for (int o = 0; o < 2; ++o) {
-                if (o < p.nout) {
-                    const real cy = real(p.cy[o]), c0 = real(p.c0[o]), c1 = real(p.c1[o]),
-                               cr = real(p.cr[o]);
-                    const A out(o == 0 ? p.out0 : p.out1, p.stride, NV);
+            for (int v = 0; v < NV; ++v) a0[v] = in0.template ld<SPOL>(v, gi);
+        }
+        if (p.nin > 1) {
+            const A in1(p.in1, p.stride, NV);
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) {
-                        real val = cy * y[v];
-                        if (p.nin > 0) val += c0 * a0[v];
-                        if (p.nin > 1) val += c1 * a1[v];
-                        val += cr * R[v];
-                        out.template st<SPOL>(v, gi, val);
-                    }
+            for (int v = 0; v < NV; ++v) a1[v] = in1.template ld<SPOL>(v, gi);
+        }
+#pragma unroll
+        for (int o = 0; o < 2; ++o) {
+            if (o < p.nout) {
+                const real cy = real(p.cy[o]), c0 = real(p.c0[o]), c1 = real(p.c1[o]),
+                           cr = real(p.cr[o]);
+                const A out(o == 0 ? p.out0 : p.out1, p.stride, NV);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    real val = cy * y[v];
+                    if (p.nin > 0) val += c0 * a0[v];
+                    if (p.nin > 1) val += c1 * a1[v];
+                    val += cr * R[v];
+                    out.template st<SPOL>(v, gi, val);
                 }
             }
         }
+    }
+}
+
+template <typename real, int DIM, int N, int EQ, bool BUF, int SPOL = 0, int YPOL = 0, int TM = 1>
+__global__ void __launch_bounds__((Geo<DIM, N, TM>::THREADS)) __attribute__((amdgpu_waves_per_eu(4)))
+stage_kernel(const StageParams p)
+{
+    using G = Geo<DIM, N, TM>;
+    __shared__ StageLds<real, DIM, N, EQ, TM> lds;
+    const ThreadSetup<DIM, N, TM> ts(p.ftab);
+    if (ts.tid < G::N1 * G::N1) lds.sD[ts.tid] = static_cast<const real *>(p.D)[ts.tid];
+    for (uint32_t vb = blockIdx.x; vb < p.ntiles32; vb += gridDim.x) {
+        // tile number: XCD-contiguous renumbering of the virtual block
+        const uint32_t xb = vb & (kXcds - 1), jb = vb / kXcds;
+        const uint32_t L = p.plain_order ? vb : xb * p.xq + (xb < p.xr ? xb : p.xr) + jb;
+        stage_tile<real, DIM, N, EQ, BUF, SPOL, YPOL, TM>(p, L, lds, ts);
+        __syncthreads();
+    }
+}
+
+// Batched stage: one launch advances every solve of one kernel class (same
+// precision, equation, dimension, degree; meshes, arrays and time steps
+// differ). Virtual tile T (XCD-contiguous numbering over all solves) belongs
+// to solve tile_solve[T] and is that solve's tile T - tile_base[solve].
+template <typename real, int DIM, int N, int EQ, bool BUF>
+__global__ void __launch_bounds__((Geo<DIM, N>::THREADS)) __attribute__((amdgpu_waves_per_eu(4)))
+stage_kernel_batch(const BatchLaunch b)
+{
+    using G = Geo<DIM, N>;
+    __shared__ StageLds<real, DIM, N, EQ, 1> lds;
+    const ThreadSetup<DIM, N, 1> ts(b.ftab);
+    if (ts.tid < G::N1 * G::N1) lds.sD[ts.tid] = static_cast<const real *>(b.D)[ts.tid];
+    for (uint32_t vb = blockIdx.x; vb < b.ntiles; vb += gridDim.x) {
+        const uint32_t xb = vb & (kXcds - 1), jb = vb / kXcds;
+        const uint32_t T = xb * b.xq + (xb < b.xr ? xb : b.xr) + jb;
+        const uint32_t s = b.tile_solve[T];
+        stage_tile<real, DIM, N, EQ, BUF, 0, 0, 1>(b.params[s], T - b.tile_base[s], lds, ts);
         __syncthreads();
     }
 }
@@ -479,6 +534,34 @@ hipError_t launch_stage(const StageParams &p, int64_t grid, hipStream_t s)
         hipLaunchKernelGGL((stage_kernel<real, DIM, N, EQ, false>), dim3((unsigned)grid),
                            dim3(Geo<DIM, N>::THREADS), 0, s, p);
     return hipGetLastError();
+}
+
+template <typename real, int DIM, int N, int EQ>
+hipError_t launch_stage_batch(const BatchLaunch &b, bool buf, int64_t grid, hipStream_t s)
+{
+    if (buf)
+        hipLaunchKernelGGL((stage_kernel_batch<real, DIM, N, EQ, true>), dim3((unsigned)grid),
+                           dim3(Geo<DIM, N>::THREADS), 0, s, b);
+    else
+        hipLaunchKernelGGL((stage_kernel_batch<real, DIM, N, EQ, false>), dim3((unsigned)grid),
+                           dim3(Geo<DIM, N>::THREADS), 0, s, b);
+    return hipGetLastError();
+}
+
+template <typename real, int DIM, int EQ>
+BatchFn pick_batch_n(int N)
+{
+    switch (N) {
+    case 1: return &launch_stage_batch<real, DIM, 1, EQ>;
+    case 2: return &launch_stage_batch<real, DIM, 2, EQ>;
+    case 3: return &launch_stage_batch<real, DIM, 3, EQ>;
+    case 4: return &launch_stage_batch<real, DIM, 4, EQ>;
+    case 5: return &launch_stage_batch<real, DIM, 5, EQ>;
+    case 6: return &launch_stage_batch<real, DIM, 6, EQ>;
+    case 7: return &launch_stage_batch<real, DIM, 7, EQ>;
+    case 8: return &launch_stage_batch<real, DIM, 8, EQ>;
+    default: return nullptr;
+    }
 }
 
 template <typename real, int DIM, int EQ>

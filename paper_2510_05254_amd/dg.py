@@ -45,7 +45,16 @@ SIGNATURES = {
     "dg_synchronize": (_I, [_P]),
     "dg_stream": (_P, [_P]),
     "dg_last_error": (ctypes.c_char_p, []),
+    "dg_batch_create": (_I, [_P, _I, _P]),
+    "dg_batch_destroy": (_I, [_P]),
+    "dg_batch_add": (_I, [_P, _P, _I, _D, _I64]),
+    "dg_batch_remove": (_I, [_P, _P]),
+    "dg_batch_run": (_I, [_P, _I64, _P]),
+    "dg_batch_remaining": (_I, [_P, _P, _P]),
+    "dg_batch_size": (_I, [_P, _P, _P]),
+    "dg_batch_synchronize": (_I, [_P]),
 }
+DG_BATCH_GRAPH = 1
 
 _lib = None
 
@@ -285,3 +294,104 @@ class Solver:
     @property
     def stream(self) -> int:
         return dg_stream(self.h)
+
+
+# --------------------------------------------------------------------------
+# batched stepping
+# --------------------------------------------------------------------------
+
+def dg_batch_create(hip_stream=None, flags=0):
+    b = ctypes.c_void_p()
+    _call("dg_batch_create", ctypes.c_void_p(hip_stream) if hip_stream else None, int(flags),
+          ctypes.byref(b))
+    return b
+
+
+def dg_batch_destroy(b):
+    if b:
+        _call("dg_batch_destroy", b)
+
+
+def dg_batch_add(b, h, rk, dt, nsteps):
+    _call("dg_batch_add", b, h, int(rk), float(dt), int(nsteps))
+
+
+def dg_batch_remove(b, h):
+    _call("dg_batch_remove", b, h)
+
+
+def dg_batch_run(b, max_steps) -> int:
+    done = ctypes.c_int64(0)
+    _call("dg_batch_run", b, int(max_steps), ctypes.byref(done))
+    return done.value
+
+
+def dg_batch_remaining(b, h) -> int:
+    r = ctypes.c_int64(0)
+    _call("dg_batch_remaining", b, h, ctypes.byref(r))
+    return r.value
+
+
+def dg_batch_size(b):
+    m, a = ctypes.c_int(0), ctypes.c_int(0)
+    _call("dg_batch_size", b, ctypes.byref(m), ctypes.byref(a))
+    return m.value, a.value
+
+
+def dg_batch_synchronize(b):
+    _call("dg_batch_synchronize", b)
+
+
+class Batch:
+    """Owning wrapper around a dg_batch handle (members are Solver objects)."""
+
+    def __init__(self, hip_stream=None, graph=False):
+        self.b = dg_batch_create(hip_stream, DG_BATCH_GRAPH if graph else 0)
+        self.members = []
+
+    def close(self):
+        if getattr(self, "b", None):
+            dg_batch_destroy(self.b)
+            self.b = None
+            self.members = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def add(self, solver, rk, dt, nsteps):
+        dg_batch_add(self.b, solver.h, rk, dt, nsteps)
+        self.members.append(solver)
+
+    def remove(self, solver):
+        dg_batch_remove(self.b, solver.h)
+        self.members.remove(solver)
+
+    def run(self, max_steps):
+        return dg_batch_run(self.b, max_steps)
+
+    def run_all(self):
+        """Run until every member has finished; returns the number of run calls."""
+        calls = 0
+        while True:
+            done = dg_batch_run(self.b, 1 << 62)
+            if done == 0:
+                return calls
+            calls += 1
+
+    def remaining(self, solver):
+        return dg_batch_remaining(self.b, solver.h)
+
+    def size(self):
+        return dg_batch_size(self.b)
+
+    def synchronize(self):
+        dg_batch_synchronize(self.b)

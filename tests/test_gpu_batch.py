@@ -1,0 +1,123 @@
+"""Batched stepping (dg_batch_*) on the GPU.
+
+A member of a batch must end exactly where dg_step on the same solver alone
+ends (same stage programs, same per-tile kernel body), and within the parity
+bar of the oracle. Covered: mixed kernel classes (1-D/2-D/3-D, advection and
+Euler, several N), different meshes and time steps in one class, members with
+different step counts, members admitted while others run (continuous
+batching), hipGraph replay of a tick with host work between replays, and the
+error paths.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2510_05254_amd import dg
+from _helpers import ADV, EUL, PARITY_RTOL, case, params, rel_l2_per_var
+
+pytestmark = pytest.mark.gpu
+
+MIX = [  # (dim, N, K, eq, rk, nsteps)
+    (1, 3, (37,), ADV, 4, 5),
+    (1, 3, (64,), ADV, 4, 9),      # same class as the first, other mesh and dt
+    (2, 2, (9, 5), EUL, 4, 4),
+    (2, 2, (3, 11), EUL, 4, 13),   # gaps of >= 4 steps: graph replays
+    (2, 7, (5, 4), ADV, 3, 6),
+    (3, 2, (4, 3, 5), EUL, 4, 3),
+    (3, 4, (3, 2, 2), EUL, 4, 18),
+    (1, 5, (10,), EUL, 3, 5),
+]
+
+
+def _solver_with_state(dim, N, K, eq, seed):
+    w, ax, U0, dt = case(dim, N, K, eq, seed)
+    s = dg.Solver(dim, N, K, eq, params(dim, eq))
+    s.set_state(U0)
+    return s, U0, dt
+
+
+def _alone(dim, N, K, eq, U0, rk, dt, n):
+    with dg.Solver(dim, N, K, eq, params(dim, eq)) as s:
+        s.set_state(U0)
+        s.step(rk, dt, n)
+        return s.get_state()
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_matches_single_solves(graph):
+    solvers, refs = [], []
+    with dg.Batch(graph=graph) as b:
+        for i, (dim, N, K, eq, rk, n) in enumerate(MIX):
+            s, U0, dt = _solver_with_state(dim, N, K, eq, 100 + i)
+            b.add(s, rk, dt, n)
+            solvers.append((s, U0, dt))
+        assert b.size() == (len(MIX), len(MIX))
+        calls = b.run_all()
+        assert calls == len(set(m[5] for m in MIX))     # one run per distinct finish time
+        assert b.size() == (len(MIX), 0)
+        for (dim, N, K, eq, rk, n), (s, U0, dt) in zip(MIX, solvers):
+            assert b.remaining(s) == 0
+            Ub = s.get_state()
+            Ua = _alone(dim, N, K, eq, U0, rk, dt, n)
+            np.testing.assert_array_equal(Ub, Ua)
+            Uo = oracle.step(dim, N, K, eq, params(dim, eq), U0, rk, dt, n)
+            assert np.all(rel_l2_per_var(Ub, Uo) <= PARITY_RTOL)
+    for s, _, _ in solvers:
+        s.close()
+
+
+def test_continuous_admission_and_graph_replays():
+    """Members join while others run; graph ticks replayed with host work between."""
+    specs = [(2, 3, (6, 5), EUL, 4, 12), (1, 4, (20,), ADV, 4, 7), (2, 3, (4, 4), EUL, 4, 9)]
+    made = [_solver_with_state(*sp[:4], seed=7 + i) for i, sp in enumerate(specs)]
+    with dg.Batch(graph=True) as b:
+        b.add(made[0][0], 4, made[0][2], specs[0][5])
+        assert b.run(3) == 3
+        mid = made[0][0].get_state()                       # host work between replays
+        np.testing.assert_array_equal(mid, _alone(*specs[0][:4], made[0][1], 4, made[0][2], 3))
+        b.add(made[1][0], 4, made[1][2], specs[1][5])       # joins the running batch
+        assert b.run(2) == 2
+        b.add(made[2][0], 4, made[2][2], specs[2][5])
+        while b.run(1 << 40):
+            pass
+        for sp, (s, U0, dt) in zip(specs, made):
+            np.testing.assert_array_equal(s.get_state(), _alone(*sp[:4], U0, 4, dt, sp[5]))
+        for s, _, _ in made:
+            b.remove(s)
+        assert b.size() == (0, 0)
+    for s, _, _ in made:
+        s.close()
+
+
+def test_batch_error_paths():
+    s, U0, dt = _solver_with_state(2, 2, (3, 3), ADV, 3)
+    fresh = dg.Solver(2, 2, (3, 3), ADV, params(2, ADV))
+    with dg.Batch() as b:
+        with pytest.raises(dg.DgError) as e:
+            b.add(s, 6, dt, 2)
+        assert e.value.status == dg.DG_ENOTSUP
+        with pytest.raises(dg.DgError) as e:
+            b.add(fresh, 4, dt, 2)
+        assert e.value.status == dg.DG_ESTATE
+        for bad in ((5, dt, 2), (4, -dt, 2), (4, dt, 0)):
+            with pytest.raises(dg.DgError) as e:
+                b.add(s, *bad)
+            assert e.value.status == dg.DG_EINVAL
+        b.add(s, 4, dt, 2)
+        with pytest.raises(dg.DgError) as e:
+            b.add(s, 4, dt, 2)
+        assert e.value.status == dg.DG_ESTATE
+        with pytest.raises(dg.DgError) as e:
+            s.step(4, dt, 1)                  # a member is stepped by its batch only
+        assert e.value.status == dg.DG_ESTATE
+        with pytest.raises(dg.DgError) as e:
+            s.set_state(U0)
+        assert e.value.status == dg.DG_ESTATE
+        with pytest.raises(dg.DgError) as e:
+            b.remove(fresh)
+        assert e.value.status == dg.DG_EINVAL
+        assert b.run(0) == 0
+        s.close()                             # destroying a member removes it
+        assert b.size() == (0, 0)
+        assert b.run(10) == 0
+    fresh.close()
