@@ -185,6 +185,80 @@ StageParams stage_program(const dg_solver *h, int rk, int s, double dt)
     return p;
 }
 
+MsPlan ms_plan(const dg_solver *h, int rk)
+{
+    MsPlan pl;
+    if (h->dim != 1 || (rk != DG_RK3 && rk != DG_RK4) || !ms_fn(h->prec, h->eq, h->N)) return pl;
+    const int64_t cap = ms_capacity(h->prec, h->eq, h->N);
+    const int64_t K = h->K[0];
+    const int stages = stage_count(rk);
+    if (K <= cap && K * h->n1 <= kMsWholeNodes) {
+        pl.whole = 1;
+        pl.smax = kMsWholeSteps;
+        pl.T = K;
+        pl.nwg = 1;
+    } else {
+        pl.smax = (int)std::max<int64_t>(1, cap / (6 * stages));
+        pl.T = cap - 2 * int64_t(stages) * pl.smax;
+        pl.nwg = (K + pl.T - 1) / pl.T;
+        if (pl.T < 1 || pl.nwg > (int64_t(1) << 31)) return MsPlan();
+    }
+    pl.ok = true;
+    return pl;
+}
+
+MsProgram ms_program(const dg_solver *h, int rk)
+{
+    MsProgram g;
+    std::memset(&g, 0, sizeof(g));
+    g.stages = stage_count(rk);
+    const void *arr[4] = {h->U, h->A, h->Ya, h->Yb};
+    auto index = [&](const void *q) -> int8_t {
+        for (int i = 0; i < 4; ++i)
+            if (arr[i] == q) return (int8_t)i;
+        return 0;
+    };
+    for (int st = 0; st < g.stages; ++st) {
+        const StageParams p = stage_program(h, rk, st, 1.0);
+        g.yin[st] = index(p.yin);
+        g.nin[st] = (int8_t)p.nin;
+        g.in0[st] = p.nin > 0 ? index(p.in0) : 0;
+        g.in1[st] = p.nin > 1 ? index(p.in1) : 0;
+        g.nout[st] = (int8_t)p.nout;
+        g.out[st][0] = index(p.out0);
+        g.out[st][1] = p.nout > 1 ? index(p.out1) : 0;
+    }
+    // the output each stage hands to the next one (the last stage's U starts
+    // the next step)
+    for (int st = 0; st < g.stages; ++st) {
+        const int8_t want = st + 1 < g.stages ? g.yin[st + 1] : g.yin[0];
+        g.next[st] = g.out[st][0] == want ? 0 : 1;
+    }
+    return g;
+}
+
+MsSolve ms_solve(const dg_solver *h, int rk, double dt, const MsPlan &pl)
+{
+    MsSolve m;
+    std::memset(&m, 0, sizeof(m));
+    m.U = h->U;
+    m.K = h->K[0];
+    m.T = pl.T;
+    m.whole = pl.whole;
+    m.rdx2 = 2.0 * (double)h->K[0];
+    m.par = h->par[0];
+    for (int st = 0; st < stage_count(rk); ++st) {
+        const StageParams p = stage_program(h, rk, st, dt);
+        for (int o = 0; o < p.nout; ++o) {
+            m.coef[st][o][0] = p.cy[o];
+            m.coef[st][o][1] = p.c0[o];
+            m.coef[st][o][2] = p.c1[o];
+            m.coef[st][o][3] = p.cr[o];
+        }
+    }
+    return m;
+}
+
 namespace {
 
 int launch(dg_solver *h, const StageParams &p)
@@ -248,6 +322,26 @@ int step_rk34(dg_solver *h, int rk, double dt)
     for (int st = 0; st < stage_count(rk); ++st) {
         int rc = launch(h, stage_program(h, rk, st, dt));
         if (rc) return rc;
+    }
+    return DG_OK;
+}
+
+// 1-D RK3/RK4: temporally blocked launches of up to smax steps each
+int step_ms(dg_solver *h, int rk, double dt, int64_t nsteps, const MsPlan &pl)
+{
+    MsLaunch L;
+    std::memset(&L, 0, sizeof(L));
+    L.solves = nullptr;
+    L.D = h->Dtab;
+    L.one = ms_solve(h, rk, dt, pl);
+    L.prog = ms_program(h, rk);
+    L.nwg = (uint32_t)pl.nwg;
+    const MsFn fn = ms_fn(h->prec, h->eq, h->N);
+    for (int64_t done = 0; done < nsteps;) {
+        const int s = (int)std::min<int64_t>(pl.smax, nsteps - done);
+        L.nsteps = s;
+        DG_HIP(fn(L, h->stream), "multi-step kernel launch");
+        done += s;
     }
     return DG_OK;
 }
@@ -605,6 +699,8 @@ int dg_step(dg_solver *h, int rk, double dt, int64_t nsteps)
     int rc = select_device(h);
     if (rc) return rc;
     if (rk == DG_RK6 && (rc = ensure_rk6(h))) return rc;
+    const MsPlan pl = ms_plan(h, rk);
+    if (pl.ok) return step_ms(h, rk, dt, nsteps, pl);
     for (int64_t s = 0; s < nsteps; ++s) {
         rc = rk == DG_RK6 ? step_rk6(h, dt) : step_rk34(h, rk, dt);
         if (rc) return rc;

@@ -22,9 +22,11 @@ using namespace dg;
 
 namespace {
 
-// A graph of one tick is captured (once per membership) only for runs of at
-// least this many ticks; shorter runs launch directly, since capture and
-// instantiation cost more than a few direct launches.
+// A graph of one tick (the per-stage launches of the 2-D/3-D classes) is
+// captured once per membership, for the first run of at least this many
+// ticks; shorter runs launch directly, since capture and instantiation cost
+// more than a few direct launches. 1-D classes are advanced by the
+// temporally blocked kernel, up to smax steps per launch.
 constexpr int64_t kGraphMinTicks = 4;
 
 struct Member {
@@ -37,6 +39,13 @@ struct Member {
 struct Group {
     int prec = 0, eq = 0, dim = 0, N = 0, rk = 0, stages = 0;
     BatchFn fn = nullptr;
+    // 1-D classes step with the temporally blocked kernel: per member an
+    // MsSolve (header, at off_params) and its workgroups; up to smax steps
+    // per launch
+    bool ms = false;
+    MsFn msfn = nullptr;
+    MsProgram prog{};
+    int smax = 0;
     bool buf = true;
     std::vector<int> idx;          // member indices
     uint32_t ntiles = 0;
@@ -99,6 +108,12 @@ int rebuild(dg_batch *b)
             g.stages = stage_count(m.rk);
             g.fn = batch_fn(h->prec, h->eq, h->dim, h->N);
             if (!g.fn) return fail(DG_ENOTSUP, "no batched kernel for this class");
+            if (ms_plan(h, m.rk).ok) {
+                g.ms = true;
+                g.msfn = ms_fn(h->prec, h->eq, h->N);
+                g.prog = ms_program(h, m.rk);
+                g.smax = kMsWholeSteps;
+            }
             g.D = h->Dtab;
             g.ftab = h->ftab;
             key[k] = (int)b->groups.size();
@@ -117,6 +132,13 @@ int rebuild(dg_batch *b)
         uint64_t tiles = 0;
         for (int i : g.idx) {
             const dg_solver *h = b->members[i].h;
+            if (g.ms) {
+                const MsPlan pl = ms_plan(h, b->members[i].rk);
+                if (!pl.ok) return fail(DG_ENOTSUP, "no multi-step plan for a 1-D member");
+                tiles += (uint64_t)pl.nwg;
+                g.smax = std::min(g.smax, pl.smax);
+                continue;
+            }
             tiles += (uint64_t)h->ntiles;
             const int64_t bytes = h->nodes * h->nvar * (h->prec == DG_FP64 ? 8 : 4);
             if (bytes >= (int64_t(1) << 31)) g.buf = false;
@@ -124,7 +146,7 @@ int rebuild(dg_batch *b)
         if (tiles >= (uint64_t(1) << 32)) return fail(DG_ENOTSUP, "batch too large for one launch");
         g.ntiles = (uint32_t)tiles;
         g.off_params = header;
-        header = round_up(header + sizeof(StageParams) * n * g.stages);
+        header = round_up(header + (g.ms ? sizeof(MsSolve) * n : sizeof(StageParams) * n * g.stages));
         g.off_base = header;
         header = round_up(header + sizeof(uint32_t) * (n + 1));
         g.grid = std::min<int64_t>((int64_t)tiles, kMaxGrid);
@@ -143,8 +165,14 @@ int rebuild(dg_batch *b)
         uint32_t t0 = 0;
         for (size_t j = 0; j < n; ++j) {
             const Member &m = b->members[g.idx[j]];
-            for (int s = 0; s < g.stages; ++s) par[s * n + j] = stage_program(m.h, m.rk, s, m.dt);
             base[j] = t0;
+            if (g.ms) {
+                const MsPlan pl = ms_plan(m.h, m.rk);
+                reinterpret_cast<MsSolve *>(par)[j] = ms_solve(m.h, m.rk, m.dt, pl);
+                t0 += (uint32_t)pl.nwg;
+                continue;
+            }
+            for (int s = 0; s < g.stages; ++s) par[s * n + j] = stage_program(m.h, m.rk, s, m.dt);
             t0 += (uint32_t)m.h->ntiles;
         }
         base[n] = t0;
@@ -181,7 +209,7 @@ int launch_tick(dg_batch *b)
     for (const Group &g : b->groups) smax = std::max(smax, g.stages);
     for (int s = 0; s < smax; ++s)
         for (const Group &g : b->groups) {
-            if (s >= g.stages) continue;
+            if (g.ms || s >= g.stages) continue;
             const uint32_t n = (uint32_t)g.idx.size();
             BatchLaunch L;
             L.params = reinterpret_cast<const StageParams *>(b->dbuf + g.off_params) + (size_t)s * n;
@@ -317,7 +345,29 @@ int dg_batch_run(dg_batch *b, int64_t max_steps, int64_t *steps_done)
         if ((rc = rebuild(b))) return rc;
         b->dirty = false;
     }
-    if ((b->flags & DG_BATCH_GRAPH) && (b->gexec || steps >= kGraphMinTicks)) {
+    bool ticked = false;
+    for (const Group &g : b->groups) {
+        if (!g.ms) {
+            ticked = true;
+            continue;
+        }
+        MsLaunch L;
+        std::memset(&L, 0, sizeof(L));
+        L.solves = reinterpret_cast<const MsSolve *>(b->dbuf + g.off_params);
+        L.wg_solve = reinterpret_cast<const uint32_t *>(b->dbuf + g.off_solve);
+        L.wg_base = reinterpret_cast<const uint32_t *>(b->dbuf + g.off_base);
+        L.D = g.D;
+        L.prog = g.prog;
+        L.nwg = g.ntiles;
+        for (int64_t done = 0; done < steps;) {
+            L.nsteps = (int)std::min<int64_t>(g.smax, steps - done);
+            DG_HIP(g.msfn(L, b->stream), "batched multi-step kernel launch");
+            done += L.nsteps;
+        }
+    }
+    if (!ticked) {
+        // every group stepped by the multi-step kernel
+    } else if ((b->flags & DG_BATCH_GRAPH) && (b->gexec || steps >= kGraphMinTicks)) {
         if (!b->gexec) {
             DG_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
             rc = launch_tick(b);

@@ -80,4 +80,25 @@ int stage_count(int rk);
 // Parameters of fused stage s of the RK3/RK4 schedule with step dt.
 StageParams stage_program(const dg_solver *h, int rk, int s, double dt);
 
+// 1-D multi-step plan: whole mode (one workgroup holds the periodic mesh,
+// up to kMsWholeSteps steps per launch) when the mesh fits in one
+// workgroup's LDS with at most kMsWholeNodes nodes; otherwise chunked, with
+// at most smax steps per launch so the halo (stages * smax elements per
+// side) stays within a sixth of the capacity, and T owned elements per
+// workgroup.
+constexpr int kMsWholeSteps = 4096;
+constexpr int64_t kMsWholeNodes = 2048;
+struct MsPlan {
+    bool ok = false;
+    int whole = 0;
+    int smax = 0;
+    int64_t T = 0;
+    int64_t nwg = 0;
+};
+MsPlan ms_plan(const dg_solver *h, int rk);
+// Stage program of scheme rk as array indices (0 U, 1 A, 2 Ya, 3 Yb).
+MsProgram ms_program(const dg_solver *h, int rk);
+// Per-solve multi-step parameters (coefficients for step dt).
+MsSolve ms_solve(const dg_solver *h, int rk, double dt, const MsPlan &pl);
+
 }  // namespace dg

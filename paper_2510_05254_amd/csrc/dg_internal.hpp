@@ -113,6 +113,45 @@ struct CastParams {
     int64_t n;
 };
 
+// ---------------------------------------------------------------------------
+// Temporally blocked 1-D stepping (dg_multistep.hpp): one launch advances
+// 1-D solves by nsteps whole RK3/RK4 steps with the RK arrays held in LDS.
+// Array indices in a program: 0 = U, 1 = A, 2 = Ya, 3 = Yb.
+// ---------------------------------------------------------------------------
+struct MsProgram {
+    int stages;
+    int8_t yin[4], nin[4], in0[4], in1[4], nout[4], out[4][2];
+    int8_t next[4];        // output (0/1) that is the next stage's input
+};
+
+struct MsSolve {
+    void *U;               // state, canonical layout (read first, written last)
+    int64_t K;             // elements
+    int64_t T;             // owned elements per workgroup (chunked mode)
+    int whole;             // 1: one workgroup holds the whole periodic mesh
+    int pad;
+    double rdx2;           // 2 / dx
+    double par;            // advection speed a, or sound speed c_s
+    double coef[4][2][4];  // per stage and output: cy, c0, c1, cr
+};
+
+struct MsLaunch {
+    const MsSolve *solves;     // device array (batched), or nullptr: use `one`
+    const uint32_t *wg_solve;  // batched: solve of each workgroup
+    const uint32_t *wg_base;   // batched: first workgroup of each solve
+    const void *D;             // (N+1)^2 differentiation matrix (state precision)
+    MsSolve one;
+    MsProgram prog;
+    uint32_t nwg;              // workgroups
+    int nsteps;                // steps per launch (halo = stages * nsteps)
+};
+
+typedef hipError_t (*MsFn)(const MsLaunch &l, hipStream_t s);
+// Multi-step launcher for 1-D (precision, equation, N); nullptr if not built.
+MsFn ms_fn(int precision, int equation, int N);
+// Elements one multi-step workgroup holds in LDS (halo included).
+int ms_capacity(int precision, int equation, int N);
+
 typedef hipError_t (*StageFn)(const StageParams &p, int64_t grid, hipStream_t s);
 typedef hipError_t (*BatchFn)(const BatchLaunch &b, bool buf, int64_t grid, hipStream_t s);
 

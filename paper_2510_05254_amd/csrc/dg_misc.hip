@@ -31,6 +31,29 @@ BatchFn batch_fn_f32_d2_euler(int N);
 BatchFn batch_fn_f32_d3_adv(int N);
 BatchFn batch_fn_f32_d3_euler(int N);
 
+MsFn ms_fn_f64_adv(int N);
+MsFn ms_fn_f64_euler(int N);
+MsFn ms_fn_f32_adv(int N);
+MsFn ms_fn_f32_euler(int N);
+int ms_cap_f64_adv(int N);
+int ms_cap_f64_euler(int N);
+int ms_cap_f32_adv(int N);
+int ms_cap_f32_euler(int N);
+
+MsFn ms_fn(int precision, int equation, int N)
+{
+    if (precision < 0 || precision > 1 || equation < 0 || equation > 1) return nullptr;
+    if (precision == 0) return equation == 0 ? ms_fn_f64_adv(N) : ms_fn_f64_euler(N);
+    return equation == 0 ? ms_fn_f32_adv(N) : ms_fn_f32_euler(N);
+}
+
+int ms_capacity(int precision, int equation, int N)
+{
+    if (precision < 0 || precision > 1 || equation < 0 || equation > 1) return 0;
+    if (precision == 0) return equation == 0 ? ms_cap_f64_adv(N) : ms_cap_f64_euler(N);
+    return equation == 0 ? ms_cap_f32_adv(N) : ms_cap_f32_euler(N);
+}
+
 BatchFn batch_fn(int precision, int equation, int dim, int N)
 {
     typedef BatchFn (*Pick)(int);

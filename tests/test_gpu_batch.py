@@ -1,7 +1,7 @@
 """Batched stepping (dg_batch_*) on the GPU.
 
 A member of a batch must end exactly where dg_step on the same solver alone
-ends (same stage programs, same per-tile kernel body), and within the parity
+ends (same stage programs and kernel bodies), and within the parity
 bar of the oracle. Covered: mixed kernel classes (1-D/2-D/3-D, advection and
 Euler, several N), different meshes and time steps in one class, members with
 different step counts, members admitted while others run (continuous
@@ -26,6 +26,8 @@ MIX = [  # (dim, N, K, eq, rk, nsteps)
     (3, 2, (4, 3, 5), EUL, 4, 3),
     (3, 4, (3, 2, 2), EUL, 4, 18),
     (1, 5, (10,), EUL, 3, 5),
+    (1, 7, (1500,), ADV, 4, 27),   # 1-D, chunked: several multi-step launches
+    (1, 7, (90,), ADV, 4, 9),      # same class, held whole by one workgroup
 ]
 
 

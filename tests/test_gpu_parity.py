@@ -57,6 +57,45 @@ def test_parity_special_meshes(dim, N, K, eq):
     assert np.all(rel_l2_per_var(Ug, Uo) <= PARITY_RTOL)
 
 
+# 1-D RK3/RK4 run temporally blocked (several steps per launch, arrays in
+# LDS). Meshes too large for one workgroup are split into chunks with halos:
+# these cases have several chunks with a ragged last one and step counts above
+# the per-launch limit, so several launches run back to back.
+@pytest.mark.parametrize("N,K,eq,rk,nsteps", [
+    (7, 1500, ADV, 4, 30), (1, 5000, ADV, 4, 70), (3, 700, EUL, 4, 9),
+    (8, 400, EUL, 3, 11), (4, 450, ADV, 3, 40), (2, 1201, EUL, 4, 5),
+])
+def test_parity_1d_chunked_multistep(N, K, eq, rk, nsteps):
+    w, ax, U0, dt = case(1, N, (K,), eq, 77)
+    with dg.Solver(1, N, (K,), eq, params(1, eq)) as s:
+        s.set_state(U0)
+        m0 = s.mass()
+        s.step(rk, dt, nsteps)
+        Ug = s.get_state()
+        m1 = s.mass()
+    Uo = oracle.step(1, N, (K,), eq, params(1, eq), U0, rk, dt, nsteps)
+    assert np.all(rel_l2_per_var(Ug, Uo) <= PARITY_RTOL)
+    assert rel_l2_per_var(Uo, U0).max() > 1e3 * PARITY_RTOL
+    scale = np.abs(U0).reshape(U0.shape[0], -1).max(axis=1)
+    assert np.all(np.abs(m1 - m0) <= 1e-14 * np.maximum(scale, 1.0))
+
+
+def test_parity_1d_whole_mesh_many_steps():
+    """A mesh held by one workgroup, stepped past the per-launch step limit.
+    Over 4100 steps the N = 1 solution decays by about 1e5, so rounding is
+    measured against the initial state's norm (as for the full-length 1-D
+    configuration run)."""
+    N, K, eq = 1, (8,), ADV
+    w, ax, U0, dt = case(1, N, K, eq, 5)
+    with dg.Solver(1, N, K, eq, params(1, eq)) as s:
+        s.set_state(U0)
+        s.step(4, dt, 4100)
+        Ug = s.get_state()
+    Uo = oracle.step(1, N, K, eq, params(1, eq), U0, 4, dt, 4100)
+    assert np.linalg.norm(Ug - Uo) <= PARITY_RTOL * np.linalg.norm(U0)
+    assert np.linalg.norm(Uo) < 0.1 * np.linalg.norm(U0)        # the long run really happened
+
+
 @pytest.mark.parametrize("dim,N,eq", [(1, 5, EUL), (2, 3, EUL), (3, 4, EUL), (3, 2, ADV)])
 def test_conservation_and_determinism(dim, N, eq):
     K = ragged_K(dim, N)
@@ -76,8 +115,8 @@ def test_conservation_and_determinism(dim, N, eq):
     np.testing.assert_array_equal(U1, U2)            # bitwise repeatable
 
 
-def test_checkpoint_split_is_bitwise():
-    dim, N, K, eq = 2, 4, (5, 3), EUL
+@pytest.mark.parametrize("dim,N,K,eq", [(2, 4, (5, 3), EUL), (1, 7, (1500,), ADV)])
+def test_checkpoint_split_is_bitwise(dim, N, K, eq):
     w, ax, U0, dt = case(dim, N, K, eq)
     with dg.Solver(dim, N, K, eq, params(dim, eq)) as s:
         s.set_state(U0)
