@@ -1,0 +1,85 @@
+"""Reduce two rocprofv3 counter runs of bench.py to measured HBM bytes per
+stage-kernel launch.
+
+    python -m paper_2510_05254_amd.traffic --fetch F.csv --write W.csv \
+        --workload euler3d_64x64x64_N4 --precision fp64 --out profiles/...json
+
+F.csv / W.csv are the counter_collection.csv files of `rocprofv3 --pmc
+FETCH_SIZE` and `rocprofv3 --pmc WRITE_SIZE` over the same bench.py command.
+The raw counters are scaled by what they read for bench.py's own calibration
+copies in the same run (device-to-device copies of exactly 2 GiB, the largest
+copyBuffer dispatches), so bytes = counter * (2 GiB / counter of the copy).
+The output records the source hash of the stage kernel so bench.py drops it
+once the kernel changes.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+import statistics
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+COPY_BYTES = 1 << 31                  # bench.py: torch.empty(1 << 28, float64)
+KERNEL_SOURCES = ["paper_2510_05254_amd/csrc/dg_stage.hpp"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def per_dispatch(path: str, counter: str):
+    """[(kernel name, value)] per dispatch, summed over the counter's instances."""
+    vals = {}
+    for r in csv.DictReader(open(path)):
+        if r.get("Counter_Name") != counter:
+            continue
+        key = (r["Dispatch_Id"], r["Kernel_Name"])
+        vals[key] = vals.get(key, 0.0) + float(r["Counter_Value"])
+    return [(name, v) for (_, name), v in sorted(vals.items(), key=lambda kv: int(kv[0][0]))]
+
+
+def reduce(path: str, counter: str, kernel: str):
+    rows = per_dispatch(path, counter)
+    copies = [v for name, v in rows if "copyBuffer" in name]
+    if not copies:
+        raise SystemExit(f"{path}: no copyBuffer dispatch to calibrate {counter}")
+    top = max(copies)
+    cal = [v for v in copies if v >= 0.9 * top]
+    factor = COPY_BYTES / statistics.median(cal)
+    ks = [v for name, v in rows if kernel in name]
+    if not ks:
+        raise SystemExit(f"{path}: no dispatch of {kernel}")
+    return {"counter": counter, "bytes_per_unit": factor, "calibration_dispatches": len(cal),
+            "kernel_dispatches": len(ks), "kernel_mean_units": statistics.mean(ks),
+            "bytes_per_launch": statistics.mean(ks) * factor}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--workload", required=True)
+    ap.add_argument("--precision", required=True)
+    ap.add_argument("--kernel", default="stage_kernel")
+    ap.add_argument("--command", default="", help="the profiled command, recorded as is")
+    ap.add_argument("--out", required=True)
+    a = ap.parse_args()
+    f = reduce(a.fetch, "FETCH_SIZE", a.kernel)
+    w = reduce(a.write, "WRITE_SIZE", a.kernel)
+    rec = {"workload": a.workload, "precision": a.precision, "kernel": a.kernel,
+           "kernel_hash": kernel_hash(),
+           "bytes_per_launch": f["bytes_per_launch"] + w["bytes_per_launch"],
+           "fetch": f, "write": w, "command": a.command}
+    with open(a.out, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()
