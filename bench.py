@@ -3,6 +3,7 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 4] [--precision fp64]
     python bench.py --serve [--requests 2000] [--time-scale 0.01] [--rates 1]
+    python bench.py --efficiency
 
 A step is one classical RK4 step (four fused RHS + stage launches) over the
 whole mesh of the chosen workload; default: 3-D isothermal Euler, 64^3
@@ -28,6 +29,14 @@ first at saturation (every request arrives at time 0) for the capacity C in
 solves/s, then with Poisson arrivals at each rate multiple of C; each run is
 repeated one solve at a time (FIFO, dg_step alone) on the same GPU. Prints one
 JSON line with solves/s and p50/p99 latency (completion - arrival) per run.
+
+--efficiency repeats the paper's error-versus-computing-time study (Sec. 3.1):
+2-D advection with a = (1, 0) over one revolution (T = 1) from
+U0 = sum_{k=1}^{40} A_k sin(2 pi k x) (seeded A_k ~ U[0,1)), (a) spatial order
+N+1 = 3..8 with RK6 and (b) RK3/RK4/RK6 at order 8, each on a ladder of square
+meshes; dt = 0.1 dx_min / |a|. Error = relative L2 distance to U0 after the
+revolution (the exact solution); time = GPU time of all steps (HIP events).
+Prints one JSON line per run.
 """
 from __future__ import annotations
 
@@ -158,6 +167,41 @@ def serve_main(a):
     print(json.dumps(out), flush=True)
 
 
+def efficiency_main(a):
+    import torch
+    from paper_2510_05254_amd import dg
+    from paper_2510_05254_amd import workloads as W
+
+    torch.cuda.init()
+    ladder = {2: (16, 32, 64, 128, 256, 512), 3: (16, 32, 64, 128, 256, 512),
+              4: (8, 16, 32, 64, 128, 256), 5: (8, 16, 32, 64, 128, 256),
+              6: (8, 16, 32, 64, 96, 128), 7: (8, 16, 32, 48, 64, 96, 128)}
+    runs = [(N, 6, K) for N in range(2, 8) for K in ladder[N]]
+    runs += [(7, rk, K) for rk in (3, 4) for K in ladder[7]]
+    for N, rk, K in runs:
+        w = W.Workload(f"adv2d_Nk40_K{K}_N{N}", 2, N, (K, K), W.ADVECTION, (1.0, 0.0), "fourier1d",
+                       W.SEED_BASE + 6, rk=rk, t_final=1.0, ic_args={"nk": 40})
+        stream = torch.cuda.Stream()
+        with dg.Solver(2, N, (K, K), W.ADVECTION, (1.0, 0.0), hip_stream=stream.cuda_stream) as s:
+            ax = s.axis_coords()
+            U0 = W.initial_state(w, ax)
+            dt, n = W.time_step(w, ax, U0)
+            s.set_state(U0)
+            s.step(rk, dt, 1)                       # warm-up (kernel load)
+            s.set_state(U0)
+            s.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            s.step(rk, dt, n)
+            e1.record(stream)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1)
+            _, rel = s.l2_error(U0)                  # one revolution: the exact solution is U0
+        print(json.dumps({"study": "error_vs_time_adv2d_Nk40", "order": N + 1, "N": N, "rk": rk,
+                          "K": [K, K], "steps": n, "dt": dt, "gpu_seconds": ms / 1e3,
+                          "rel_l2_error": rel, "unknowns": w.unknowns}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -175,6 +219,7 @@ def main():
     ap.add_argument("--arena-gib", type=float, default=32.0)
     ap.add_argument("--chunk", type=int, default=32)
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--efficiency", action="store_true", help="error vs computing time study")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -182,6 +227,9 @@ def main():
         sys.exit(2)
     if a.serve:
         serve_main(a)
+        return
+    if a.efficiency:
+        efficiency_main(a)
         return
 
     import torch
