@@ -213,8 +213,7 @@ struct StageLds {
 template <int DIM, int N, int TM>
 struct ThreadSetup {
     int tid, slot, n, ijk[3];
-    uint32_t fw0, fw1, fw2, fw3;    // this thread's first face point
-    __device__ __forceinline__ ThreadSetup(const uint32_t *ftab)
+    __device__ __forceinline__ ThreadSetup()
     {
         using G = Geo<DIM, N, TM>;
         tid = threadIdx.x;
@@ -223,13 +222,6 @@ struct ThreadSetup {
         ijk[0] = n % G::N1;
         ijk[1] = DIM > 1 ? (n / G::N1) % G::N1 : 0;
         ijk[2] = DIM > 2 ? n / (G::N1 * G::N1) : 0;
-        fw0 = fw1 = fw2 = fw3 = 0;
-        if (tid < G::NF) {
-            fw0 = ftab[4 * tid + 0];
-            fw1 = ftab[4 * tid + 1];
-            fw2 = ftab[4 * tid + 2];
-            fw3 = ftab[4 * tid + 3];
-        }
     }
 };
 
@@ -238,7 +230,7 @@ struct ThreadSetup {
 template <typename real, int DIM, int N, int EQ, bool BUF, int SPOL, int YPOL, int TM>
 __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
                                            StageLds<real, DIM, N, EQ, TM> &lds,
-                                           const ThreadSetup<DIM, N, TM> &ts)
+                                           const ThreadSetup<DIM, N, TM> &ts, real dval)
 {
     using G = Geo<DIM, N, TM>;
     constexpr int N1 = G::N1, NP = G::NP, NF1 = G::NF1, EPB = G::EPB;
@@ -254,7 +246,6 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
     auto &sD = lds.sD;
     const int tid = ts.tid, slot = ts.slot, n = ts.n;
     const int *ijk = ts.ijk;
-    const uint32_t fw0 = ts.fw0, fw1 = ts.fw1, fw2 = ts.fw2, fw3 = ts.fw3;
 
     const A yin(p.yin, p.stride, NV);
     real par[3], rdx2[3];
@@ -285,54 +276,71 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
     const int nact = (int)((K0 - ex0) < EPB ? (K0 - ex0) : EPB);
     const int64_t ebase = K0 * (ey + K1 * ez);     // element index of (0, ey, ez)
 
-    // Face point fields (see dg_tables.cpp): w0 = d | own_slot << 2 |
-    // (other_slot+1) << 10 | other_is_lower << 18 | kind << 19,
-    // w1 = own_node | other_node << 16, w2 = plane or slot, w3 = lift slots.
-    auto face_valid = [&](uint32_t w0, uint32_t ps) {
-        return ((w0 >> 19) & 3u) == 0 ? ps <= uint32_t(nact) : ps < uint32_t(nact);
-    };
-    auto other_outside = [&](uint32_t w0, uint32_t ps) {
-        return ((w0 >> 10) & 0xffu) == 0 || (((w0 >> 19) & 3u) == 0 && ps == uint32_t(nact));
-    };
-    // element holding the other side when it lies outside the tile
-    auto outside_elem = [&](uint32_t w0, uint32_t ps) -> int64_t {
-        const int d = int(w0 & 3u), kind = int((w0 >> 19) & 3u);
-        if (kind == 0) {
-            int64_t ex = ((w0 >> 18) & 1u) ? ex0 - 1 : ex0 + nact;
-            if (ex < 0) ex += K0;
-            if (ex >= K0) ex -= K0;
-            return ebase + ex;
-        }
-        int64_t yy = ey, zz = ez;
-        const int step = kind == 2 ? 1 : -1;
-        if (d == 1) {
-            yy += step;
-            if (yy < 0) yy += K1;
-            if (yy >= K1) yy -= K1;
-        } else {
-            zz += step;
-            if (zz < 0) zz += K2;
-            if (zz >= K2) zz -= K2;
-        }
-        return ex0 + int64_t(ps) + K0 * (yy + K1 * zz);
-    };
-
-    // ---- prefetch the outside state of this thread's first face point
-    real g[NV];
-    if (tid < NF && face_valid(fw0, fw2) && other_outside(fw0, fw2)) {
-        const idx_t gn = idx_t(outside_elem(fw0, fw2) * NP + (fw1 >> 16));
-#pragma unroll
-        for (int v = 0; v < NV; ++v) g[v] = yin.ld(v, gn);
+    // Neighbour element bases (node offsets) of this tile, uniform: bsel =
+    // 2 d + 1 for the upper neighbour along d, 2 d for the lower one (x: the
+    // elements left of the tile and right of its last active slot; y, z: the
+    // row of elements above/below the tile).
+    auto wrap = [](int64_t e, int64_t K) { return e < 0 ? e + K : (e >= K ? e - K : e); };
+    // named values, not an array: a select over array elements becomes a
+    // dynamically indexed (scratch) load
+    const idx_t nb0 = idx_t((ebase + wrap(ex0 - 1, K0)) * NP);
+    const idx_t nb1 = idx_t((ebase + wrap(ex0 + nact, K0)) * NP);
+    idx_t nb2 = 0, nb3 = 0, nb4 = 0, nb5 = 0;
+    if constexpr (DIM > 1) {
+        nb2 = idx_t((ex0 + K0 * (wrap(ey - 1, K1) + K1 * ez)) * NP);
+        nb3 = idx_t((ex0 + K0 * (wrap(ey + 1, K1) + K1 * ez)) * NP);
     }
+    if constexpr (DIM > 2) {
+        nb4 = idx_t((ex0 + K0 * (ey + K1 * wrap(ez - 1, K2))) * NP);
+        nb5 = idx_t((ex0 + K0 * (ey + K1 * wrap(ez + 1, K2))) * NP);
+    }
+    // Face point fields (see dg_tables.cpp): w0 = d | other_is_lower << 2 |
+    // bsel << 3 | other_in_tile << 6 | need << 8 | xplane << 16,
+    // w1 = own_q | other_q << 16, w2 = outside node offset, w3 = lift slots.
+    auto face_valid = [nact](uint32_t w0) { return ((w0 >> 8) & 0xffu) <= uint32_t(nact); };
+    auto other_outside = [nact](uint32_t w0) {
+        return ((w0 >> 6) & 1u) == 0 || ((w0 >> 16) & 0xffu) == uint32_t(nact);
+    };
+    // blend of the six bases by masks (bitwise, so it stays in registers)
+    auto outside_node = [nb0, nb1, nb2, nb3, nb4, nb5](uint32_t w0, uint32_t w2) -> idx_t {
+        using U = typename std::make_unsigned<idx_t>::type;
+        const uint32_t bsel = (w0 >> 3) & 7u;
+        auto m = [bsel](uint32_t k) { return U(0) - U(bsel == k); };
+        U b = (U(nb0) & m(0)) | (U(nb1) & m(1));
+        if constexpr (DIM > 1) b |= (U(nb2) & m(2)) | (U(nb3) & m(3));
+        if constexpr (DIM > 2) b |= (U(nb4) & m(4)) | (U(nb5) & m(5));
+        return idx_t(b) + idx_t(w2);
+    };
 
-    // ---- phase 1: state, 1/rho and flux tensor into LDS
+    // ---- phase 1: state, 1/rho and flux tensor into LDS; the outside trace
+    // of this thread's first face point is prefetched behind the own state.
     const bool active = slot < nact;
     const int ln = slot * NP + n;
     const idx_t gi = idx_t((ebase + ex0 + slot) * NP + n);
-    real y[NV];
-    if (active) {
+    // both groups are loaded unconditionally (inactive lanes read node 0) so
+    // the wait before the LDS stores covers only the first group
+    // Issue order matters (vector loads retire in order): this thread's first
+    // face-point descriptor, then the own state, then (once the descriptor is
+    // in) the outside trace; phase 1 then waits for the own state only.
+    uint32_t fw0 = 0, fw1 = 0, fw2 = 0, fw3 = 0;
+    if (tid < NF) {
+        fw0 = p.ftab[4 * tid + 0];
+        fw1 = p.ftab[4 * tid + 1];
+        fw2 = p.ftab[4 * tid + 2];
+        fw3 = p.ftab[4 * tid + 3];
+    }
+    real y[NV], g[NV];
+    const idx_t gy = active ? gi : idx_t(0);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) y[v] = yin.template ld<YPOL>(v, gi);
+    for (int v = 0; v < NV; ++v) y[v] = yin.template ld<YPOL>(v, gy);
+    const bool pre = tid < NF && face_valid(fw0) && other_outside(fw0);
+    const idx_t gn0 = pre ? outside_node(fw0, fw2) : idx_t(0);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) g[v] = yin.ld(v, gn0);
+    // D (loaded at kernel entry into dval, stored here so the entry does not
+    // wait for it before the tile's loads are issued)
+    if (tid < N1 * N1) sD[tid] = dval;
+    if (active) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) sY[v][ln] = y[v];
         if constexpr (EQ == 1) {
@@ -361,16 +369,16 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
             w2 = p.ftab[4 * f + 2];
             w3 = p.ftab[4 * f + 3];
         }
-        if (!face_valid(w0, w2)) continue;
-        const bool oglob = other_outside(w0, w2);
+        if (!face_valid(w0)) continue;
+        const bool oglob = other_outside(w0);
         if (f >= THREADS && oglob) {
-            const idx_t gn = idx_t(outside_elem(w0, w2) * NP + (w1 >> 16));
+            const idx_t gn = outside_node(w0, w2);
 #pragma unroll
             for (int v = 0; v < NV; ++v) g[v] = yin.ld(v, gn);
         }
-        const int own_q = int((w0 >> 2) & 0xffu) * NP + int(w1 & 0xffffu);
-        const int oth_q = (int((w0 >> 10) & 0xffu) - 1) * NP + int(w1 >> 16);
-        const bool oth_lower = (w0 >> 18) & 1u;
+        const int own_q = int(w1 & 0xffffu);
+        const int oth_q = int(w1 >> 16);
+        const bool oth_lower = (w0 >> 2) & 1u;
         const int own_l = int(w3 & 0xffffu), oth_l = int(w3 >> 16);
         auto face = [&](auto dconst) {
             constexpr int D = decltype(dconst)::value;
@@ -491,13 +499,13 @@ stage_kernel(const StageParams p)
 {
     using G = Geo<DIM, N, TM>;
     __shared__ StageLds<real, DIM, N, EQ, TM> lds;
-    const ThreadSetup<DIM, N, TM> ts(p.ftab);
-    if (ts.tid < G::N1 * G::N1) lds.sD[ts.tid] = static_cast<const real *>(p.D)[ts.tid];
+    const ThreadSetup<DIM, N, TM> ts;
+    const real dval = ts.tid < G::N1 * G::N1 ? static_cast<const real *>(p.D)[ts.tid] : real(0);
     for (uint32_t vb = blockIdx.x; vb < p.ntiles32; vb += gridDim.x) {
         // tile number: XCD-contiguous renumbering of the virtual block
         const uint32_t xb = vb & (kXcds - 1), jb = vb / kXcds;
         const uint32_t L = p.plain_order ? vb : xb * p.xq + (xb < p.xr ? xb : p.xr) + jb;
-        stage_tile<real, DIM, N, EQ, BUF, SPOL, YPOL, TM>(p, L, lds, ts);
+        stage_tile<real, DIM, N, EQ, BUF, SPOL, YPOL, TM>(p, L, lds, ts, dval);
         __syncthreads();
     }
 }
@@ -512,13 +520,13 @@ stage_kernel_batch(const BatchLaunch b)
 {
     using G = Geo<DIM, N>;
     __shared__ StageLds<real, DIM, N, EQ, 1> lds;
-    const ThreadSetup<DIM, N, 1> ts(b.ftab);
-    if (ts.tid < G::N1 * G::N1) lds.sD[ts.tid] = static_cast<const real *>(b.D)[ts.tid];
+    const ThreadSetup<DIM, N, 1> ts;
+    const real dval = ts.tid < G::N1 * G::N1 ? static_cast<const real *>(b.D)[ts.tid] : real(0);
     for (uint32_t vb = blockIdx.x; vb < b.ntiles; vb += gridDim.x) {
         const uint32_t xb = vb & (kXcds - 1), jb = vb / kXcds;
         const uint32_t T = xb * b.xq + (xb < b.xr ? xb : b.xr) + jb;
         const uint32_t s = b.tile_solve[T];
-        stage_tile<real, DIM, N, EQ, BUF, 0, 0, 1>(b.params[s], T - b.tile_base[s], lds, ts);
+        stage_tile<real, DIM, N, EQ, BUF, 0, 0, 1>(b.params[s], T - b.tile_base[s], lds, ts, dval);
         __syncthreads();
     }
 }

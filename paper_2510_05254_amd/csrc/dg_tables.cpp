@@ -11,14 +11,17 @@
 //             element along d (global memory).
 // Each face point has an "own" side inside the tile and an "other" side
 // (inside the tile only for x-planes between two tile slots). Entry (4 x uint32):
-//   w0 = d | own_slot << 2 | (other_slot+1) << 10 | other_is_lower << 18 | kind << 19
-//        (other_slot+1 = 0: the other side lies outside the tile; kind 0 x-plane,
-//         1 lower face of slot s, 2 upper face of slot s)
-//   w1 = own_node | other_node << 16   node of each side inside its element
-//   w2 = pl or s                       (plane or slot, for the ragged-tile test)
+//   w0 = d | other_is_lower << 2 | bsel << 3 | other_in_tile << 6 | need << 8 | xplane << 16
+//        need:   the point is active iff need <= nact, the tile's active slots
+//                (x-plane pl: need = pl; face of slot s: need = s + 1);
+//        xplane: pl for x-planes, 0xff otherwise; the other side of plane nact
+//                of a ragged tile lies outside the tile;
+//        bsel:   which neighbour element base holds an outside other side:
+//                2 d + (1 if that element is the upper neighbour);
+//   w1 = own_q | other_q << 16   tile node index (slot * Np + node) of each side
+//   w2 = goff                    node offset of an outside other side from its
+//                                neighbour base (x: node; y/z: s * Np + node)
 //   w3 = own_lift | other_lift << 16   lift slots of the two sides
-// For x-planes the table assumes a full tile; the kernel treats plane nact of
-// a ragged tile (nact < EPB active slots) as having its other side outside.
 #include <cstdint>
 #include <vector>
 
@@ -77,10 +80,18 @@ void build_face_table(int dim, int N, int epb, uint32_t *tab)
                 own_lift = lift((int)d, s, 1, t);
             }
         }
-        tab[4 * f + 0] = d | (uint32_t)own_slot << 2 | (uint32_t)(oth_slot + 1) << 10 | oth_lower << 18 |
-                         kind << 19;
-        tab[4 * f + 1] = own_node | oth_node << 16;
-        tab[4 * f + 2] = ps;
+        const uint32_t NP = (uint32_t)ipow_h(N1, dim);
+        const uint32_t in_tile = oth_slot >= 0 ? 1u : 0u;
+        const uint32_t upper_nb = oth_lower ? 0u : 1u;
+        const uint32_t bsel = 2 * d + upper_nb;
+        const uint32_t need = kind == 0 ? ps : ps + 1;
+        const uint32_t xplane = kind == 0 ? ps : 0xffu;
+        const uint32_t own_q = (uint32_t)own_slot * NP + own_node;
+        const uint32_t oth_q = in_tile ? (uint32_t)oth_slot * NP + oth_node : 0u;
+        const uint32_t goff = kind == 0 ? oth_node : ps * NP + oth_node;
+        tab[4 * f + 0] = d | oth_lower << 2 | bsel << 3 | in_tile << 6 | need << 8 | xplane << 16;
+        tab[4 * f + 1] = own_q | oth_q << 16;
+        tab[4 * f + 2] = goff;
         tab[4 * f + 3] = own_lift | oth_lift << 16;
     }
 }
