@@ -36,12 +36,14 @@ template <typename real, int N, int EQ>
 struct Geo1 {
     static constexpr int N1 = N + 1;
     static constexpr int NV = EQ == 0 ? 1 : 2;
-    static constexpr int THREADS = 256;
-    // RK arrays U, A, Ya, Yb, plus (Euler) the flux of the current and the
-    // next stage input, in about 80 KB of LDS (two workgroups per CU)
-    static constexpr int PER_NODE = (4 + (EQ == 1 ? 2 : 0)) * NV * (int)sizeof(real);
-    static constexpr int CAP_E = (80 * 1024 - N1 * N1 * (int)sizeof(real)) / PER_NODE / N1;
-    static constexpr int CAP = CAP_E * N1;       // nodes
+    // one thread per element: an element's nodes sit at an odd stride S >= N+1
+    // (in doubles) so lanes reading element-strided LDS hit distinct banks
+    static constexpr int S = (N1 % 2) ? N1 : N1 + 1;
+    static constexpr int PER_ELEM = 4 * NV * S * (int)sizeof(real);    // U, A, Ya, Yb
+    static constexpr int BUDGET = 80 * 1024 - N1 * N1 * (int)sizeof(real);
+    // elements held (a multiple of 64); threads take one element per pass
+    static constexpr int CAP_E = ((BUDGET / PER_ELEM) / 64) * 64;
+    static constexpr int THREADS = CAP_E < 256 ? CAP_E : 256;
 };
 
 __device__ __forceinline__ double rcp_nr(double x)
@@ -88,13 +90,12 @@ __device__ __forceinline__ void lf_flux(const real *UL, const real *FL, real lam
 }
 
 template <typename real, int N, int EQ>
-__global__ void __launch_bounds__(256) ms1_kernel(const MsLaunch l)
+__global__ void __launch_bounds__((Geo1<real, N, EQ>::THREADS)) ms1_kernel(const MsLaunch l)
 {
     using G = Geo1<real, N, EQ>;
-    constexpr int N1 = G::N1, NV = G::NV, CAP = G::CAP;
+    constexpr int N1 = G::N1, NV = G::NV, S = G::S, CAP_E = G::CAP_E, THREADS = G::THREADS;
     constexpr real INVW0 = real(N * (N + 1)) / real(2);    // 1/w_0 = 1/w_N
-    __shared__ real sA[4][NV][CAP];                         // U, A, Ya, Yb
-    __shared__ real sF[EQ == 1 ? 2 : 1][NV][EQ == 1 ? CAP : 1];
+    __shared__ real sA[4][NV][CAP_E * S];                   // U, A, Ya, Yb
     __shared__ real sD[N1 * N1];
 
     const int tid = threadIdx.x;
@@ -118,33 +119,23 @@ __global__ void __launch_bounds__(256) ms1_kernel(const MsLaunch l)
     const real sl = rdx2 * INVW0;
 
     if (tid < N1 * N1) sD[tid] = static_cast<const real *>(l.D)[tid];
-    // ---- load U over the local range (periodic wrap by one period at most)
-    for (int idx = tid; idx < L * N1; idx += G::THREADS) {
+    // ---- load U over the local range (node-parallel, coalesced; periodic
+    // wrap by one period at most)
+    for (int idx = tid; idx < L * N1; idx += THREADS) {
         const int le = idx / N1, i = idx - le * N1;
         int64_t ge = gfirst + le;
         if (ge < 0) ge += K;
         if (ge >= K) ge -= K;
-        real u[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            u[v] = U[v * stride + ge * N1 + i];
-            sA[0][v][idx] = u[v];
-        }
-        if constexpr (EQ == 1) {
-            real F[NV], lam;
-            flux1<real, EQ>(u, par, F, lam);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) sF[0][v][idx] = F[v];
-        }
+        for (int v = 0; v < NV; ++v) sA[0][v][le * S + i] = U[v * stride + ge * N1 + i];
     }
     __syncthreads();
 
     int a = 0, b = L;          // elements on which the current stage input is valid
-    int fc = 0;                // sF buffer holding F(stage input) (Euler)
     for (int step = 0; step < l.nsteps; ++step) {
         for (int st = 0; st < stages; ++st) {
             const int yi = l.prog.yin[st], nin = l.prog.nin[st], nout = l.prog.nout[st];
-            const int i0 = l.prog.in0[st], i1 = l.prog.in1[st], nx = l.prog.next[st];
+            const int i0 = l.prog.in0[st], i1 = l.prog.in1[st];
             const int lo = whole ? 0 : a + 1, hi = whole ? L : b - 1;
             real cy[2], c0[2], c1[2], cr[2];
             int oi[2];
@@ -156,81 +147,82 @@ __global__ void __launch_bounds__(256) ms1_kernel(const MsLaunch l)
                 cr[o] = real(P->coef[st][o][3]);
                 oi[o] = l.prog.out[st][o];
             }
-            for (int idx = lo * N1 + tid; idx < hi * N1; idx += G::THREADS) {
-                const int le = idx / N1, i = idx - le * N1;
-                const int base = le * N1;
-                // volume term
-                real acc[NV];
-#pragma unroll
-                for (int v = 0; v < NV; ++v) acc[v] = real(0);
+            for (int le = lo + tid; le < hi; le += THREADS) {
+                const int base = le * S;
+                // the element's stage input and fluxes, in registers
+                real u[N1][NV], F[N1][NV], lam0, lamN;
 #pragma unroll
                 for (int m = 0; m < N1; ++m) {
-                    const real dm = sD[i * N1 + m];
 #pragma unroll
-                    for (int v = 0; v < NV; ++v)
-                        acc[v] += dm * (EQ == 0 ? sA[yi][v][base + m] : sF[fc][v][base + m]);
+                    for (int v = 0; v < NV; ++v) u[m][v] = sA[yi][v][base + m];
+                    real lam;
+                    flux1<real, EQ>(u[m], par, F[m], lam);
+                    if (m == 0) lam0 = lam;
+                    if (m == N) lamN = lam;
                 }
-                real R[NV];
+                // volume term
+                real R[N1][NV];
 #pragma unroll
-                for (int v = 0; v < NV; ++v) R[v] = real(0);
-                if constexpr (EQ == 0) {
-                    R[0] -= rdx2 * (par * acc[0]);
-                } else {
+                for (int i = 0; i < N1; ++i) {
+                    real acc[NV];
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) R[v] -= rdx2 * acc[v];
-                }
-                // faces: lower face at node 0, upper face at node N
-                if (i == 0 || i == N) {
-                    const int lower = i == 0 ? (le == 0 ? (whole ? L - 1 : -1) : le - 1) : le;
-                    const int upper = i == 0 ? le : (le == L - 1 ? (whole ? 0 : -1) : le + 1);
-                    const int ql = lower * N1 + N, qu = upper * N1;
-                    real UL[NV], UR[NV], FL[NV], FR[NV], lamL, lamR, Fh[NV];
+                    for (int v = 0; v < NV; ++v) acc[v] = real(0);
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) {
-                        UL[v] = sA[yi][v][ql];
-                        UR[v] = sA[yi][v][qu];
+                    for (int m = 0; m < N1; ++m) {
+                        const real dm = sD[i * N1 + m];
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) acc[v] += dm * (EQ == 0 ? u[m][v] : F[m][v]);
                     }
-                    flux1<real, EQ>(UL, par, FL, lamL);
-                    flux1<real, EQ>(UR, par, FR, lamR);
-                    lf_flux<real, NV>(UL, FL, lamL, UR, FR, lamR, Fh);
 #pragma unroll
-                    for (int v = 0; v < NV; ++v)
-                        R[v] += i == 0 ? sl * (Fh[v] - FR[v]) : -sl * (Fh[v] - FL[v]);
+                    for (int v = 0; v < NV; ++v) R[i][v] = real(0);
+                    if constexpr (EQ == 0) {
+                        R[i][0] -= rdx2 * (par * acc[0]);
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) R[i][v] -= rdx2 * acc[v];
+                    }
+                }
+                // lower face (with element le-1) and upper face (with le+1);
+                // each face is evaluated by both elements from the same
+                // (lower, upper) pair
+                {
+                    const int ln = le == 0 ? L - 1 : le - 1;       // chunked: le >= 1
+                    const int un = le == L - 1 ? 0 : le + 1;       // chunked: le <= L-2
+                    real Un[NV], Fn[NV], lamn, Fh[NV];
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) Un[v] = sA[yi][v][ln * S + N];
+                    flux1<real, EQ>(Un, par, Fn, lamn);
+                    lf_flux<real, NV>(Un, Fn, lamn, u[0], F[0], lam0, Fh);
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) R[0][v] += sl * (Fh[v] - F[0][v]);
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) Un[v] = sA[yi][v][un * S];
+                    flux1<real, EQ>(Un, par, Fn, lamn);
+                    lf_flux<real, NV>(u[N], F[N], lamN, Un, Fn, lamn, Fh);
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) R[N][v] += -sl * (Fh[v] - F[N][v]);
                 }
                 // RK stage combination
-                real y[NV], a0[NV], a1[NV];
 #pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    y[v] = sA[yi][v][idx];
-                    a0[v] = nin > 0 ? sA[i0][v][idx] : real(0);
-                    a1[v] = nin > 1 ? sA[i1][v][idx] : real(0);
-                }
+                for (int i = 0; i < N1; ++i) {
 #pragma unroll
-                for (int o = 0; o < 2; ++o) {
-                    if (o < nout) {
-                        real out[NV];
+                    for (int v = 0; v < NV; ++v) {
+                        const real a0 = nin > 0 ? sA[i0][v][base + i] : real(0);
+                        const real a1 = nin > 1 ? sA[i1][v][base + i] : real(0);
 #pragma unroll
-                        for (int v = 0; v < NV; ++v) {
-                            real val = cy[o] * y[v];
-                            if (nin > 0) val += c0[o] * a0[v];
-                            if (nin > 1) val += c1[o] * a1[v];
-                            val += cr[o] * R[v];
-                            out[v] = val;
-                            sA[oi[o]][v][idx] = val;
-                        }
-                        if constexpr (EQ == 1) {
-                            if (o == nx) {
-                                real F[NV], lam;
-                                flux1<real, EQ>(out, par, F, lam);
-#pragma unroll
-                                for (int v = 0; v < NV; ++v) sF[fc ^ 1][v][idx] = F[v];
+                        for (int o = 0; o < 2; ++o) {
+                            if (o < nout) {
+                                real val = cy[o] * u[i][v];
+                                if (nin > 0) val += c0[o] * a0;
+                                if (nin > 1) val += c1[o] * a1;
+                                val += cr[o] * R[i][v];
+                                sA[oi[o]][v][base + i] = val;
                             }
                         }
                     }
                 }
             }
             __syncthreads();
-            if constexpr (EQ == 1) fc ^= 1;
             if (!whole) {
                 ++a;
                 --b;
@@ -238,11 +230,11 @@ __global__ void __launch_bounds__(256) ms1_kernel(const MsLaunch l)
         }
     }
     // ---- write back the owned elements
-    for (int idx = H * N1 + tid; idx < (H + town) * N1; idx += G::THREADS) {
+    for (int idx = H * N1 + tid; idx < (H + town) * N1; idx += THREADS) {
         const int le = idx / N1, i = idx - le * N1;
         const int64_t ge = gfirst + le;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) U[v * stride + ge * N1 + i] = sA[0][v][idx];
+        for (int v = 0; v < NV; ++v) U[v * stride + ge * N1 + i] = sA[0][v][le * S + i];
     }
 }
 
