@@ -329,6 +329,17 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
         fw2 = p.ftab[4 * tid + 2];
         fw3 = p.ftab[4 * tid + 3];
     }
+    // the second face point of threads that have one (tiles with more face
+    // points than threads), read and prefetched here too so phase 2 does not
+    // wait on two dependent global loads
+    constexpr bool PASS2 = NF > THREADS;
+    uint32_t fx0 = 0, fx1 = 0, fx2 = 0, fx3 = 0;
+    if (PASS2 && tid + THREADS < NF) {
+        fx0 = p.ftab[4 * (tid + THREADS) + 0];
+        fx1 = p.ftab[4 * (tid + THREADS) + 1];
+        fx2 = p.ftab[4 * (tid + THREADS) + 2];
+        fx3 = p.ftab[4 * (tid + THREADS) + 3];
+    }
     real y[NV], g[NV];
     const idx_t gy = active ? gi : idx_t(0);
 #pragma unroll
@@ -337,6 +348,13 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
     const idx_t gn0 = pre ? outside_node(fw0, fw2) : idx_t(0);
 #pragma unroll
     for (int v = 0; v < NV; ++v) g[v] = yin.ld(v, gn0);
+    real g2[NV];
+    if constexpr (PASS2) {
+        const bool pre2 = tid + THREADS < NF && face_valid(fx0) && other_outside(fx0);
+        const idx_t gn2 = pre2 ? outside_node(fx0, fx2) : idx_t(0);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) g2[v] = yin.ld(v, gn2);
+    }
     // D (loaded at kernel entry into dval, stored here so the entry does not
     // wait for it before the tile's loads are issued)
     if (tid < N1 * N1) sD[tid] = dval;
@@ -363,7 +381,11 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
     // commutes and both factors of the product change sign exactly).
     for (int f = tid; f < NF; f += THREADS) {
         uint32_t w0 = fw0, w1 = fw1, w2 = fw2, w3 = fw3;
-        if (f >= THREADS) {
+        if (PASS2 && f >= THREADS && f < 2 * THREADS) {
+            w0 = fx0; w1 = fx1; w2 = fx2; w3 = fx3;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) g[v] = g2[v];
+        } else if (f >= 2 * THREADS) {
             w0 = p.ftab[4 * f + 0];
             w1 = p.ftab[4 * f + 1];
             w2 = p.ftab[4 * f + 2];
@@ -371,7 +393,7 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
         }
         if (!face_valid(w0)) continue;
         const bool oglob = other_outside(w0);
-        if (f >= THREADS && oglob) {
+        if (f >= 2 * THREADS && oglob) {
             const idx_t gn = outside_node(w0, w2);
 #pragma unroll
             for (int v = 0; v < NV; ++v) g[v] = yin.ld(v, gn);
