@@ -220,6 +220,9 @@ def main():
     ap.add_argument("--chunk", type=int, default=32)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--efficiency", action="store_true", help="error vs computing time study")
+    ap.add_argument("--autotune", action="store_true",
+                    help="autotune the launch configuration before timing (the committed traffic "
+                         "counters are for the default configuration)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -249,6 +252,9 @@ def main():
     t_ic = time.perf_counter() - t0
     s.set_state(U0)
     m0 = s.mass()
+    # launch configuration: the default, or autotuned before the timed region
+    # (every candidate computes the same results)
+    launch_cfg = s.autotune(a.rk, dt, 3) if a.autotune else s.launch_config()
 
     s.step(a.rk, dt, a.warmup)
     s.synchronize()
@@ -312,6 +318,9 @@ def main():
                      "traffic": traffic,
                      "kernel": "stage_kernel", "alg_bytes_per_launch": alg_bytes,
                      "avg_launch_us": avg_launch_s * 1e6},
+        "launch_config": {"tile_order": "plain" if launch_cfg[0] else "xcd_contiguous",
+                          "z_slab": launch_cfg[1], "halo_divisor_1d": launch_cfg[2],
+                          "autotuned": bool(launch_cfg[3])},
         "nodes_per_s": w.nodes * stages * a.steps / (ms / 1e3),
         "copy_gbps": copy_gbs,
         "mass_drift": (np.abs(m1 - m0) / np.maximum(np.abs(m0), 1.0)).max(),

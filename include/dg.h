@@ -157,6 +157,24 @@ int dg_synchronize(dg_solver *h);
 /* The solver's hipStream_t (as void*), for stream-ordered interop. */
 void *dg_stream(const dg_solver *h);
 
+/* Autotune the launch configuration for stepping h with scheme rk and step
+ * dt: times trial_steps (1..1000) steps of each candidate on the solver's
+ * arrays, restarting from a saved copy of the state, restores the state and
+ * keeps the fastest candidate for later dg_step calls. Candidates: 3-D, the
+ * tile order (XCD-contiguous or plain) and the z-slab size; 2-D, the tile
+ * order; 1-D RK3/RK4 meshes split into chunks, the steps per launch (via the
+ * halo bound). Every candidate computes the same results bit for bit; only
+ * speed differs. Synchronous. Needs a library-owned workspace (DG_ENOTSUP
+ * otherwise: it allocates one state-sized copy); DG_ESTATE before the first
+ * set_state or for a batch member. */
+int dg_autotune(dg_solver *h, int rk, double dt, int trial_steps);
+
+/* The launch configuration in use: cfg[0] tile order (0 XCD-contiguous,
+ * 1 plain), cfg[1] z-slab size, cfg[2] 1-D halo-bound divisor (steps per
+ * launch = capacity / (cfg[2] * stages)), cfg[3] 1 once autotuned. Writes
+ * min(n, 4) entries and zeros beyond. */
+int dg_launch_config(const dg_solver *h, int64_t *cfg, int n);
+
 /* ---------------------------------------------------------------------------
  * Batched stepping (many solves advanced together; the method per solve is
  * unchanged: every member takes the same RK steps it would take alone).

@@ -122,6 +122,7 @@ StageParams base_params(const dg_solver *h)
     p.fd_slab = make_fastdiv((uint32_t)h->slab);
     p.fd_k1 = make_fastdiv((uint32_t)h->K[1]);
     p.ftab = h->ftab;
+    p.plain_order = (uint32_t)h->plain_order;
     return p;
 }
 
@@ -198,7 +199,7 @@ MsPlan ms_plan(const dg_solver *h, int rk)
         pl.T = K;
         pl.nwg = 1;
     } else {
-        pl.smax = (int)std::max<int64_t>(1, cap / (6 * stages));
+        pl.smax = (int)std::max<int64_t>(1, cap / (int64_t(h->ms_div) * stages));
         pl.T = cap - 2 * int64_t(stages) * pl.smax;
         pl.nwg = (K + pl.T - 1) / pl.T;
         if (pl.T < 1 || pl.nwg > (int64_t(1) << 31)) return MsPlan();
@@ -786,6 +787,97 @@ int dg_synchronize(dg_solver *h)
     int rc = select_device(h);
     if (rc) return rc;
     DG_HIP(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    return DG_OK;
+}
+
+int dg_autotune(dg_solver *h, int rk, double dt, int trial_steps)
+{
+    if (!h) return fail(DG_EINVAL, "solver is NULL");
+    if (rk != DG_RK3 && rk != DG_RK4 && rk != DG_RK6) return fail(DG_EINVAL, "rk must be 3, 4 or 6");
+    if (!std::isfinite(dt) || !(dt > 0.0)) return fail(DG_EINVAL, "dt must be finite and > 0");
+    if (trial_steps < 1 || trial_steps > 1000) return fail(DG_EINVAL, "trial_steps must be in 1..1000");
+    if (!h->has_state) return fail(DG_ESTATE, "dg_set_state has not been called");
+    if (h->batch) return fail(DG_ESTATE, "solver belongs to a batch");
+    if (!h->own_ws) return fail(DG_ENOTSUP, "autotuning needs a library-owned workspace");
+    int rc = select_device(h);
+    if (rc) return rc;
+    if (rk == DG_RK6 && (rc = ensure_rk6(h))) return rc;
+
+    // candidate launch configurations (tile order, z-slab, 1-D halo bound)
+    struct Cfg { int plain, ms_div; int64_t slab; };
+    std::vector<Cfg> cand;
+    const bool ms = ms_plan(h, rk).ok;
+    if (ms) {
+        if (!ms_plan(h, rk).whole)
+            for (int dv : {3, 4, 6, 10, 16}) cand.push_back({h->plain_order, dv, h->slab});
+    } else if (h->dim == 3) {
+        for (int plain = 0; plain <= 1; ++plain)
+            for (int64_t sl = 1; sl <= h->K[2]; sl *= 2)
+                if (h->K[2] % sl == 0) cand.push_back({plain, h->ms_div, sl});
+    } else {
+        for (int plain = 0; plain <= 1; ++plain) cand.push_back({plain, h->ms_div, h->slab});
+    }
+    if (cand.size() < 2) {
+        h->tuned = 1;
+        return DG_OK;
+    }
+    // time each candidate on the solver's own arrays from a saved copy of U,
+    // then restore U
+    void *save = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMalloc(&save, h->lay.array);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(DG_ENOMEM, "cannot allocate the autotuning copy of the state");
+    }
+    rc = DG_OK;
+    Cfg best = cand[0];
+    float best_ms = -1.0f;
+    const Cfg keep = {h->plain_order, h->ms_div, h->slab};
+    e = hipMemcpyAsync(save, h->U, h->lay.array, hipMemcpyDeviceToDevice, h->stream);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    for (size_t i = 0; e == hipSuccess && rc == DG_OK && i < cand.size(); ++i) {
+        h->plain_order = cand[i].plain;
+        h->ms_div = cand[i].ms_div;
+        h->slab = cand[i].slab;
+        rc = dg_step(h, rk, dt, 1);                                   // warm-up
+        if (rc) break;
+        e = hipMemcpyAsync(h->U, save, h->lay.array, hipMemcpyDeviceToDevice, h->stream);
+        if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
+        if (e != hipSuccess) break;
+        rc = dg_step(h, rk, dt, trial_steps);
+        if (rc) break;
+        e = hipEventRecord(e1, h->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms_t = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms_t, e0, e1);
+        if (e == hipSuccess && (best_ms < 0.0f || ms_t < best_ms)) {
+            best_ms = ms_t;
+            best = cand[i];
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(h->U, save, h->lay.array, hipMemcpyDeviceToDevice, h->stream);
+    }
+    if (e == hipSuccess && rc == DG_OK) e = hipStreamSynchronize(h->stream);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(save);
+    const Cfg use = (e == hipSuccess && rc == DG_OK) ? best : keep;
+    h->plain_order = use.plain;
+    h->ms_div = use.ms_div;
+    h->slab = use.slab;
+    if (rc) return rc;
+    if (e != hipSuccess) return hip_fail(e, "autotuning");
+    h->tuned = 1;
+    return DG_OK;
+}
+
+int dg_launch_config(const dg_solver *h, int64_t *cfg, int n)
+{
+    if (!h || !cfg || n < 0) return fail(DG_EINVAL, "NULL argument or n < 0");
+    const int64_t v[4] = {h->plain_order, h->slab, h->ms_div, h->tuned};
+    for (int i = 0; i < n && i < 4; ++i) cfg[i] = v[i];
+    for (int i = 4; i < n; ++i) cfg[i] = 0;
     return DG_OK;
 }
 

@@ -67,6 +67,12 @@ struct dg_solver {
     dg::StageFn stage = nullptr;
     int epb = 0;
     int64_t tiles_x = 0, slab = 1, ntiles = 0, grid = 0;
+    // launch configuration (dg_autotune may change it; results do not depend
+    // on it): tile order 0 XCD-contiguous / 1 plain; 1-D steps per launch
+    // follow from the halo bound capacity / (ms_div * stages)
+    int plain_order = 0;
+    int ms_div = 6;
+    int tuned = 0;
     dg_batch *batch = nullptr;      // batch this solver belongs to, if any
 };
 
@@ -84,8 +90,8 @@ StageParams stage_program(const dg_solver *h, int rk, int s, double dt);
 // up to kMsWholeSteps steps per launch) when the mesh fits in one
 // workgroup's LDS with at most kMsWholeNodes nodes; otherwise chunked, with
 // at most smax steps per launch so the halo (stages * smax elements per
-// side) stays within a sixth of the capacity, and T owned elements per
-// workgroup.
+// side) stays within capacity / ms_div (6 unless tuned), and T owned
+// elements per workgroup.
 constexpr int kMsWholeSteps = 4096;
 constexpr int64_t kMsWholeNodes = 2048;
 struct MsPlan {

@@ -44,6 +44,8 @@ SIGNATURES = {
     "dg_mass": (_I, [_P, _P]),
     "dg_synchronize": (_I, [_P]),
     "dg_stream": (_P, [_P]),
+    "dg_autotune": (_I, [_P, _I, _D, _I]),
+    "dg_launch_config": (_I, [_P, _P, _I]),
     "dg_last_error": (ctypes.c_char_p, []),
     "dg_batch_create": (_I, [_P, _I, _P]),
     "dg_batch_destroy": (_I, [_P]),
@@ -220,6 +222,17 @@ def dg_synchronize(h):
     _call("dg_synchronize", h)
 
 
+def dg_autotune(h, rk, dt, trial_steps=3):
+    _call("dg_autotune", h, int(rk), float(dt), int(trial_steps))
+
+
+def dg_launch_config(h):
+    """(tile order, z-slab, 1-D halo-bound divisor, tuned flag)."""
+    out = (ctypes.c_int64 * 4)()
+    _call("dg_launch_config", h, out, 4)
+    return tuple(int(x) for x in out)
+
+
 def dg_stream(h) -> int:
     return load().dg_stream(h) or 0
 
@@ -287,6 +300,13 @@ class Solver:
 
     def mass(self):
         return dg_mass(self.h)
+
+    def autotune(self, rk, dt, trial_steps=3):
+        dg_autotune(self.h, rk, dt, trial_steps)
+        return dg_launch_config(self.h)
+
+    def launch_config(self):
+        return dg_launch_config(self.h)
 
     def synchronize(self):
         dg_synchronize(self.h)

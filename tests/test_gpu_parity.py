@@ -231,3 +231,44 @@ def test_fp32_against_fp64_oracle(dim, N, eq):
     print(f"fp32 dim={dim} N={N} eq={eq} rel L2 per var {err}")
     assert np.all(err <= 2e-6), err
     np.testing.assert_allclose(m, oracle.mass(dim, N, K, eq, Uo), rtol=1e-6, atol=1e-7)
+
+
+# The autotuner times launch configurations that all compute the same bits:
+# afterwards the state is the one set, and stepping gives bitwise what the
+# default configuration gives.
+@pytest.mark.parametrize("dim,N,K,eq,rk", [(3, 4, (6, 4, 8), EUL, 4), (2, 3, (20, 9), EUL, 4),
+                                           (1, 7, (1500,), ADV, 4), (2, 5, (7, 6), ADV, 6),
+                                           (1, 3, (40,), EUL, 3)])
+def test_autotune_keeps_state_and_results(dim, N, K, eq, rk):
+    w, ax, U0, dt = case(dim, N, K, eq, 21)
+    with dg.Solver(dim, N, K, eq, params(dim, eq)) as s:
+        s.set_state(U0)
+        s.step(rk, dt, 3)
+        ref = s.get_state()
+        s.set_state(U0)
+        cfg = s.autotune(rk, dt, 2)
+        assert cfg[3] == 1 and cfg[0] in (0, 1) and cfg[1] >= 1 and cfg[2] >= 3
+        np.testing.assert_array_equal(s.get_state(), U0)
+        s.step(rk, dt, 3)
+        np.testing.assert_array_equal(s.get_state(), ref)
+
+
+def test_autotune_error_paths():
+    import torch
+    w, ax, U0, dt = case(2, 2, (4, 3), ADV, 3)
+    with dg.Solver(2, 2, (4, 3), ADV, params(2, ADV)) as s:
+        with pytest.raises(dg.DgError) as e:
+            s.autotune(4, dt)
+        assert e.value.status == dg.DG_ESTATE
+        s.set_state(U0)
+        for bad in ((5, dt, 2), (4, -dt, 2), (4, dt, 0)):
+            with pytest.raises(dg.DgError) as e:
+                s.autotune(*bad)
+            assert e.value.status == dg.DG_EINVAL
+    ws = dg.dg_workspace_bytes(2, 2, (4, 3), ADV)
+    buf = torch.empty(ws, dtype=torch.uint8, device="cuda")
+    with dg.Solver(2, 2, (4, 3), ADV, params(2, ADV), device_workspace=buf, workspace_bytes=ws) as s:
+        s.set_state(U0)
+        with pytest.raises(dg.DgError) as e:
+            s.autotune(4, dt)
+        assert e.value.status == dg.DG_ENOTSUP
