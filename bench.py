@@ -54,8 +54,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "NDG DOF-updates/s per RK stage + %HBM peak; served solves/s with p50/p99"
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, AMD public specification
-PASSES_PER_STEP = {4: 14, 3: 9}
-STAGES = {4: 4, 3: 3}
+# state-array passes per step of the fused schedules: RK4 2+4+5+3, RK3 3+3+3,
+# RK6 (stage s reads Y_s, U and the k's it combines, writes k_s and Y_s+1)
+# 4+5+6+7+8+9+7
+PASSES_PER_STEP = {4: 14, 3: 9, 6: 46}
+STAGES = {4: 4, 3: 3, 6: 7}
 KERNEL_SOURCES = ["paper_2510_05254_amd/csrc/dg_stage.hpp"]
 
 
@@ -209,7 +212,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=4)
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
-    ap.add_argument("--rk", type=int, choices=[3, 4], default=4)
+    ap.add_argument("--rk", type=int, choices=[3, 4, 6], default=4)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve", action="store_true", help="served-stream benchmark")

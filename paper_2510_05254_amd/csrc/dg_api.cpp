@@ -268,16 +268,6 @@ int launch(dg_solver *h, const StageParams &p)
     return DG_OK;
 }
 
-// RK6 k-store stage: k = dt F(yin)
-int run_k_stage(dg_solver *h, const void *yin, void *k, double dt)
-{
-    StageParams p = base_params(h);
-    p.yin = yin;
-    p.nin = 0;
-    set_out(p, 0, k, 0.0, 0.0, 0.0, dt);
-    return launch(h, p);
-}
-
 int ensure_rk6(dg_solver *h)
 {
     if (h->kx[0]) return DG_OK;
@@ -296,25 +286,6 @@ int ensure_rk6(dg_solver *h)
         mem = h->rk6_mem;
     }
     for (int i = 0; i < 5; ++i) h->kx[i] = mem + i * h->lay.array;
-    return DG_OK;
-}
-
-int run_combine(dg_solver *h, void *out, const void *base, double a_base,
-                const std::vector<std::pair<const void *, double>> &src, double scale)
-{
-    CombineParams c;
-    std::memset(&c, 0, sizeof(c));
-    c.base = base;
-    c.a_base = a_base;
-    c.scale = scale;
-    c.nsrc = (int)src.size();
-    for (size_t j = 0; j < src.size(); ++j) {
-        c.src[j] = src[j].first;
-        c.c[j] = src[j].second;
-    }
-    c.out = out;
-    c.n = h->unknowns;
-    DG_HIP(launch_combine(h->prec, c, h->stream), "combine kernel launch");
     return DG_OK;
 }
 
@@ -382,25 +353,52 @@ const Rk6Tableau &rk6_tableau()
     return t;
 }
 
+// Luther's RK6 (eq. RK6), fused: stage s evaluates R = F(Y_s) once and writes
+//   k_s = dt R                                               (s < 6)
+//   Y_{s+1} = U + sum_{j<s} (num[s+1][j]/den[s+1]) k_j + (num[s+1][s] dt/den[s+1]) R
+// and the last stage U <- U + sum_{j<6} (bnum_j/bden) k_j + (bnum_6 dt/bden) R.
+// k_0..k_5 live in A, kx[0..4]; Y alternates between Ya and Yb.
 int step_rk6(dg_solver *h, double dt)
 {
     const Rk6Tableau &t = rk6_tableau();
-    void *k[7] = {h->A, h->Yb, h->kx[0], h->kx[1], h->kx[2], h->kx[3], h->kx[4]};
-    void *Y = h->Ya;
-    int rc;
+    void *k[6] = {h->A, h->kx[0], h->kx[1], h->kx[2], h->kx[3], h->kx[4]};
+    void *Y[2] = {h->Ya, h->Yb};
     for (int s = 0; s < 7; ++s) {
-        const void *ys = s == 0 ? h->U : Y;
-        if ((rc = run_k_stage(h, ys, k[s], dt))) return rc;
-        std::vector<std::pair<const void *, double>> src;
-        if (s < 6) {
-            for (int j = 0; j <= s; ++j)
-                if (t.num[s + 1][j] != 0.0) src.push_back({k[j], t.num[s + 1][j]});
-            if ((rc = run_combine(h, Y, h->U, 1.0, src, 1.0 / t.den[s + 1]))) return rc;
-        } else {
-            for (int j = 0; j < 7; ++j)
-                if (t.bnum[j] != 0.0) src.push_back({k[j], t.bnum[j]});
-            if ((rc = run_combine(h, h->U, h->U, 1.0, src, 1.0 / t.bden))) return rc;
+        StageParams p = base_params(h);
+        p.yin = s == 0 ? h->U : Y[(s - 1) % 2];
+        const double *num = s < 6 ? t.num[s + 1] : t.bnum;
+        const double den = s < 6 ? t.den[s + 1] : t.bden;
+        int o = 0;
+        if (s < 6) {                                   // k_s = dt R
+            set_out(p, 0, k[s], 0.0, 0.0, 0.0, dt);
+            o = 1;
         }
+        // the combination: U first, then the stored k's with nonzero weights
+        std::vector<std::pair<const void *, double>> in;
+        in.push_back({h->U, 1.0});
+        for (int j = 0; j < s && j < 6; ++j)
+            if (num[j] != 0.0) in.push_back({k[j], num[j] / den});
+        if ((int)in.size() > 2 + kMaxExtraIn) return fail(DG_ENOTSUP, "too many RK6 stage inputs");
+        void *dst = s < 6 ? Y[s % 2] : h->U;
+        (o == 0 ? p.out0 : p.out1) = dst;
+        p.cy[o] = 0.0;
+        p.cr[o] = num[s] * dt / den;
+        p.nin = (int)std::min<size_t>(2, in.size());
+        p.in0 = in[0].first;
+        p.c0[o] = in[0].second;
+        if (in.size() > 1) {
+            p.in1 = in[1].first;
+            p.c1[o] = in[1].second;
+        }
+        ExtraIn x;
+        std::memset(&x, 0, sizeof(x));
+        for (size_t j = 2; j < in.size(); ++j) {
+            x.in[x.n] = in[j].first;
+            x.c[o][x.n] = in[j].second;
+            ++x.n;
+        }
+        p.nout = o + 1;
+        DG_HIP(stage_x_fn(h->prec, h->eq, h->dim, h->N)(p, x, h->grid, h->stream), "RK6 stage kernel launch");
     }
     return DG_OK;
 }

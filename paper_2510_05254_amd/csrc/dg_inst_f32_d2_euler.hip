@@ -3,5 +3,6 @@
 
 namespace dg {
 StageFn stage_fn_f32_d2_euler(int N) { return pick_stage_n<float, 2, 1>(N); }
+StageXFn stage_x_fn_f32_d2_euler(int N) { return pick_stage_x_n<float, 2, 1>(N); }
 BatchFn batch_fn_f32_d2_euler(int N) { return pick_batch_n<float, 2, 1>(N); }
 }  // namespace dg

@@ -11,6 +11,7 @@ constexpr int kMaxN = 8;
 constexpr int kMaxNP1 = kMaxN + 1;
 constexpr int kXcds = 8;                 // MI355X: 8 accelerator complex dies
 constexpr int64_t kMaxGrid = 1 << 20;    // launch cap; blocks loop beyond it
+constexpr int kMaxExtraIn = 5;           // extra stage inputs (RK6 k-store)
 
 // Unsigned 32-bit division by an invariant divisor d as a multiply-high, add
 // and shift ("round-up" magic-number method, Granlund & Montgomery, PLDI 1994):
@@ -79,19 +80,6 @@ struct BatchLaunch {
     uint32_t ntiles, xq, xr, nsolves;
 };
 
-// Elementwise linear combination (RK6 stage assembly):
-//   out = a_base * base + (sum_j c[j] * src[j]) * scale
-struct CombineParams {
-    const void *base;
-    const void *src[8];
-    double c[8];
-    double a_base;
-    double scale;
-    int nsrc;
-    void *out;
-    int64_t n;
-};
-
 // Quadrature reductions: per-block FP64 partial sums of
 //   mode 0 (mass): sum q_n U_v
 //   mode 1 (L2):   sum q_n (U_v - Uref_v)^2  and  sum q_n Uref_v^2
@@ -152,17 +140,27 @@ MsFn ms_fn(int precision, int equation, int N);
 // Elements one multi-step workgroup holds in LDS (halo included).
 int ms_capacity(int precision, int equation, int N);
 
+// Further stage inputs of the fused RK6 stages (the stored k's), after
+// in0/in1:  out_o += sum_{j < n} c[o][j] * in[j]  (zero coefficients skipped).
+// A separate kernel argument, so the RK3/RK4 kernels do not carry it.
+struct ExtraIn {
+    const void *in[kMaxExtraIn];
+    double c[2][kMaxExtraIn];
+    int n;
+};
+
 typedef hipError_t (*StageFn)(const StageParams &p, int64_t grid, hipStream_t s);
+typedef hipError_t (*StageXFn)(const StageParams &p, const ExtraIn &x, int64_t grid, hipStream_t s);
 typedef hipError_t (*BatchFn)(const BatchLaunch &b, bool buf, int64_t grid, hipStream_t s);
 
 // Stage launcher for (precision, equation, dim, N); nullptr if not built.
 StageFn stage_fn(int precision, int equation, int dim, int N);
+StageXFn stage_x_fn(int precision, int equation, int dim, int N);
 BatchFn batch_fn(int precision, int equation, int dim, int N);
 // Threads per block and elements per block of the stage kernel for (dim, N).
 int stage_threads(int dim, int N);
 int stage_epb(int dim, int N);
 
-hipError_t launch_combine(int precision, const CombineParams &p, hipStream_t s);
 hipError_t launch_reduce(int precision, const ReduceParams &p, int64_t blocks, hipStream_t s);
 hipError_t launch_cast(int to_precision, int from_precision, const CastParams &p, hipStream_t s);
 // tile_solve[t] = j for tile_base[j] <= t < tile_base[j+1], j < nsolves

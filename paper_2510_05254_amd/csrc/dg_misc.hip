@@ -1,6 +1,6 @@
-// dg_misc.hip -- stage-kernel dispatch, the elementwise combination used to
-// assemble RK6 stages, FP64 quadrature reductions (mass, L2) and precision
-// casts between the canonical FP64 layout and the state type.
+// dg_misc.hip -- stage-kernel dispatch, FP64 quadrature reductions (mass, L2),
+// precision casts between the canonical FP64 layout and the state type, and
+// the batch tile-map fill.
 #include "dg_stage.hpp"
 
 namespace dg {
@@ -18,6 +18,18 @@ StageFn stage_fn_f32_d2_euler(int N);
 StageFn stage_fn_f32_d3_adv(int N);
 StageFn stage_fn_f32_d3_euler(int N);
 
+StageXFn stage_x_fn_f64_d1_adv(int N);
+StageXFn stage_x_fn_f64_d1_euler(int N);
+StageXFn stage_x_fn_f64_d2_adv(int N);
+StageXFn stage_x_fn_f64_d2_euler(int N);
+StageXFn stage_x_fn_f64_d3_adv(int N);
+StageXFn stage_x_fn_f64_d3_euler(int N);
+StageXFn stage_x_fn_f32_d1_adv(int N);
+StageXFn stage_x_fn_f32_d1_euler(int N);
+StageXFn stage_x_fn_f32_d2_adv(int N);
+StageXFn stage_x_fn_f32_d2_euler(int N);
+StageXFn stage_x_fn_f32_d3_adv(int N);
+StageXFn stage_x_fn_f32_d3_euler(int N);
 BatchFn batch_fn_f64_d1_adv(int N);
 BatchFn batch_fn_f64_d1_euler(int N);
 BatchFn batch_fn_f64_d2_adv(int N);
@@ -69,6 +81,21 @@ BatchFn batch_fn(int precision, int equation, int dim, int N)
     return table[precision][dim - 1][equation](N);
 }
 
+StageXFn stage_x_fn(int precision, int equation, int dim, int N)
+{
+    typedef StageXFn (*Pick)(int);
+    static const Pick table[2][3][2] = {
+        {{stage_x_fn_f64_d1_adv, stage_x_fn_f64_d1_euler},
+         {stage_x_fn_f64_d2_adv, stage_x_fn_f64_d2_euler},
+         {stage_x_fn_f64_d3_adv, stage_x_fn_f64_d3_euler}},
+        {{stage_x_fn_f32_d1_adv, stage_x_fn_f32_d1_euler},
+         {stage_x_fn_f32_d2_adv, stage_x_fn_f32_d2_euler},
+         {stage_x_fn_f32_d3_adv, stage_x_fn_f32_d3_euler}}};
+    if (precision < 0 || precision > 1 || equation < 0 || equation > 1 || dim < 1 || dim > 3)
+        return nullptr;
+    return table[precision][dim - 1][equation](N);
+}
+
 StageFn stage_fn(int precision, int equation, int dim, int N)
 {
     typedef StageFn (*Pick)(int);
@@ -106,37 +133,11 @@ int stage_epb(int dim, int N)
     return dim == 1 ? threads_n<1>(N, true) : dim == 2 ? threads_n<2>(N, true) : threads_n<3>(N, true);
 }
 
-// ---------------------------------------------------------------------------
-// out = a_base * base + (sum_j c_j src_j) * scale   (RK6 stage assembly)
-// ---------------------------------------------------------------------------
-template <typename real>
-__global__ void __launch_bounds__(256) combine_kernel(const CombineParams p)
-{
-    const real *base = static_cast<const real *>(p.base);
-    real *out = static_cast<real *>(p.out);
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < p.n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        real sum = real(0);
-        for (int j = 0; j < p.nsrc; ++j) sum += real(p.c[j]) * static_cast<const real *>(p.src[j])[i];
-        out[i] = real(p.a_base) * base[i] + sum * real(p.scale);
-    }
-}
-
 static int64_t grid_for(int64_t n, int threads)
 {
     int64_t g = (n + threads - 1) / threads;
     if (g > kMaxGrid) g = kMaxGrid;
     return g < 1 ? 1 : g;
-}
-
-hipError_t launch_combine(int precision, const CombineParams &p, hipStream_t s)
-{
-    const int64_t g = grid_for(p.n, 256);
-    if (precision == 0)
-        hipLaunchKernelGGL(combine_kernel<double>, dim3((unsigned)g), dim3(256), 0, s, p);
-    else
-        hipLaunchKernelGGL(combine_kernel<float>, dim3((unsigned)g), dim3(256), 0, s, p);
-    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

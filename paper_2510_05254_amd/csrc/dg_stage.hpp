@@ -227,10 +227,11 @@ struct ThreadSetup {
 
 // One tile (EPB consecutive elements along x) of one RHS + RK stage: tile L of
 // the solve described by p, in that solve's tile numbering.
-template <typename real, int DIM, int N, int EQ, bool BUF, int SPOL, int YPOL, int TM>
+template <typename real, int DIM, int N, int EQ, bool BUF, int SPOL, int YPOL, int TM, bool XIN = false>
 __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
                                            StageLds<real, DIM, N, EQ, TM> &lds,
-                                           const ThreadSetup<DIM, N, TM> &ts, real dval)
+                                           const ThreadSetup<DIM, N, TM> &ts, real dval,
+                                           const ExtraIn *x = nullptr)
 {
     using G = Geo<DIM, N, TM>;
     constexpr int N1 = G::N1, NP = G::NP, NF1 = G::NF1, EPB = G::EPB;
@@ -502,13 +503,33 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
                 const real cy = real(p.cy[o]), c0 = real(p.c0[o]), c1 = real(p.c1[o]),
                            cr = real(p.cr[o]);
                 const A out(o == 0 ? p.out0 : p.out1, p.stride, NV);
+                if constexpr (!XIN) {
 #pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    real val = cy * y[v];
-                    if (p.nin > 0) val += c0 * a0[v];
-                    if (p.nin > 1) val += c1 * a1[v];
-                    val += cr * R[v];
-                    out.template st<SPOL>(v, gi, val);
+                    for (int v = 0; v < NV; ++v) {
+                        real val = cy * y[v];
+                        if (p.nin > 0) val += c0 * a0[v];
+                        if (p.nin > 1) val += c1 * a1[v];
+                        val += cr * R[v];
+                        out.template st<SPOL>(v, gi, val);
+                    }
+                } else {
+                    // fused RK6 stages: also the stored k's with nonzero weights
+                    real val[NV];
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        val[v] = cy * y[v];
+                        if (p.nin > 0) val[v] += c0 * a0[v];
+                        if (p.nin > 1) val[v] += c1 * a1[v];
+                    }
+                    for (int j = 0; j < x->n; ++j) {
+                        if (x->c[o][j] == 0.0) continue;
+                        const real cj = real(x->c[o][j]);
+                        const A in(x->in[j], p.stride, NV);
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) val[v] += cj * in.template ld<SPOL>(v, gi);
+                    }
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) out.template st<SPOL>(v, gi, val[v] + cr * R[v]);
                 }
             }
         }
@@ -528,6 +549,23 @@ stage_kernel(const StageParams p)
         const uint32_t xb = vb & (kXcds - 1), jb = vb / kXcds;
         const uint32_t L = p.plain_order ? vb : xb * p.xq + (xb < p.xr ? xb : p.xr) + jb;
         stage_tile<real, DIM, N, EQ, BUF, SPOL, YPOL, TM>(p, L, lds, ts, dval);
+        __syncthreads();
+    }
+}
+
+// Single-solve stage kernel with further inputs (fused RK6 stages).
+template <typename real, int DIM, int N, int EQ, bool BUF>
+__global__ void __launch_bounds__((Geo<DIM, N>::THREADS)) __attribute__((amdgpu_waves_per_eu(4)))
+stage_kernel_x(const StageParams p, const ExtraIn x)
+{
+    using G = Geo<DIM, N>;
+    __shared__ StageLds<real, DIM, N, EQ, 1> lds;
+    const ThreadSetup<DIM, N, 1> ts;
+    const real dval = ts.tid < G::N1 * G::N1 ? static_cast<const real *>(p.D)[ts.tid] : real(0);
+    for (uint32_t vb = blockIdx.x; vb < p.ntiles32; vb += gridDim.x) {
+        const uint32_t xb = vb & (kXcds - 1), jb = vb / kXcds;
+        const uint32_t L = p.plain_order ? vb : xb * p.xq + (xb < p.xr ? xb : p.xr) + jb;
+        stage_tile<real, DIM, N, EQ, BUF, 0, 0, 1, true>(p, L, lds, ts, dval, &x);
         __syncthreads();
     }
 }
@@ -576,6 +614,35 @@ hipError_t launch_stage_batch(const BatchLaunch &b, bool buf, int64_t grid, hipS
         hipLaunchKernelGGL((stage_kernel_batch<real, DIM, N, EQ, false>), dim3((unsigned)grid),
                            dim3(Geo<DIM, N>::THREADS), 0, s, b);
     return hipGetLastError();
+}
+
+template <typename real, int DIM, int N, int EQ>
+hipError_t launch_stage_x(const StageParams &p, const ExtraIn &x, int64_t grid, hipStream_t s)
+{
+    const int64_t bytes = p.stride * Vars<EQ, DIM>::NV * (int64_t)sizeof(real);
+    if (bytes < (int64_t(1) << 31))
+        hipLaunchKernelGGL((stage_kernel_x<real, DIM, N, EQ, true>), dim3((unsigned)grid),
+                           dim3(Geo<DIM, N>::THREADS), 0, s, p, x);
+    else
+        hipLaunchKernelGGL((stage_kernel_x<real, DIM, N, EQ, false>), dim3((unsigned)grid),
+                           dim3(Geo<DIM, N>::THREADS), 0, s, p, x);
+    return hipGetLastError();
+}
+
+template <typename real, int DIM, int EQ>
+StageXFn pick_stage_x_n(int N)
+{
+    switch (N) {
+    case 1: return &launch_stage_x<real, DIM, 1, EQ>;
+    case 2: return &launch_stage_x<real, DIM, 2, EQ>;
+    case 3: return &launch_stage_x<real, DIM, 3, EQ>;
+    case 4: return &launch_stage_x<real, DIM, 4, EQ>;
+    case 5: return &launch_stage_x<real, DIM, 5, EQ>;
+    case 6: return &launch_stage_x<real, DIM, 6, EQ>;
+    case 7: return &launch_stage_x<real, DIM, 7, EQ>;
+    case 8: return &launch_stage_x<real, DIM, 8, EQ>;
+    default: return nullptr;
+    }
 }
 
 template <typename real, int DIM, int EQ>
