@@ -228,8 +228,8 @@ def main():
                          "counters are for the default configuration)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path; "
+              "run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if a.serve:
         serve_main(a)

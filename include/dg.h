@@ -62,7 +62,7 @@ enum dg_status {
     DG_EINVAL = -1,   /* invalid argument */
     DG_ENOMEM = -2,   /* device memory (or the given workspace) too small */
     DG_EDEVICE = -3,  /* no usable GPU, or a HIP call failed */
-    DG_ENOTSUP = -4,  /* valid request this build does not support */
+    DG_ENOTSUP = -4,  /* valid request the library does not support */
     DG_ESTATE = -5    /* call out of order (e.g. stepping before a state is set) */
 };
 
