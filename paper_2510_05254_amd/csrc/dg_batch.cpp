@@ -39,6 +39,7 @@ struct Member {
 struct Group {
     int prec = 0, eq = 0, dim = 0, N = 0, rk = 0, stages = 0;
     BatchFn fn = nullptr;
+    int nin[8] = {};               // RK inputs of each stage (same for every member)
     // 1-D classes step with the temporally blocked kernel: per member an
     // MsSolve (header, at off_params) and its workgroups; up to smax steps
     // per launch
@@ -108,6 +109,7 @@ int rebuild(dg_batch *b)
             g.stages = stage_count(m.rk);
             g.fn = batch_fn(h->prec, h->eq, h->dim, h->N);
             if (!g.fn) return fail(DG_ENOTSUP, "no batched kernel for this class");
+            for (int s = 0; s < g.stages; ++s) g.nin[s] = stage_program(h, m.rk, s, m.dt).nin;
             if (ms_plan(h, m.rk).ok) {
                 g.ms = true;
                 g.msfn = ms_fn(h->prec, h->eq, h->N);
@@ -221,7 +223,7 @@ int launch_tick(dg_batch *b)
             L.xq = g.ntiles / kXcds;
             L.xr = g.ntiles % kXcds;
             L.nsolves = n;
-            DG_HIP(g.fn(L, g.buf, g.grid, b->stream), "batched stage kernel launch");
+            DG_HIP(g.fn(L, g.buf, g.nin[s], g.grid, b->stream), "batched stage kernel launch");
         }
     return DG_OK;
 }

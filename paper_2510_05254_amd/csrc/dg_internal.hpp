@@ -151,7 +151,8 @@ struct ExtraIn {
 
 typedef hipError_t (*StageFn)(const StageParams &p, int64_t grid, hipStream_t s);
 typedef hipError_t (*StageXFn)(const StageParams &p, const ExtraIn &x, int64_t grid, hipStream_t s);
-typedef hipError_t (*BatchFn)(const BatchLaunch &b, bool buf, int64_t grid, hipStream_t s);
+// nin: the stage's number of RK inputs, the same for every solve of the launch
+typedef hipError_t (*BatchFn)(const BatchLaunch &b, bool buf, int nin, int64_t grid, hipStream_t s);
 
 // Stage launcher for (precision, equation, dim, N); nullptr if not built.
 StageFn stage_fn(int precision, int equation, int dim, int N);

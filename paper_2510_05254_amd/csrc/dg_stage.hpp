@@ -105,6 +105,14 @@ __device__ __forceinline__ real sym_flux(real ma, real mb, real rho, real rinv, 
     return f;
 }
 
+// a b + c rounded once
+template <typename real>
+__device__ __forceinline__ real fmadd(real a, real b, real c)
+{
+    if constexpr (sizeof(real) == 8) return __builtin_fma(a, b, c);
+    else return __builtin_fmaf(a, b, c);
+}
+
 // largest absolute eigenvalue of the isothermal Euler flux Jacobian along d
 template <typename real>
 __device__ __forceinline__ real wave_speed(real md, real rinv, real c)
@@ -226,8 +234,12 @@ struct ThreadSetup {
 };
 
 // One tile (EPB consecutive elements along x) of one RHS + RK stage: tile L of
-// the solve described by p, in that solve's tile numbering.
-template <typename real, int DIM, int N, int EQ, bool BUF, int SPOL, int YPOL, int TM, bool XIN = false>
+// the solve described by p, in that solve's tile numbering. NIN >= 0 fixes the
+// number of RK inputs (p.nin) at compile time, so their loads are issued in
+// phase 1 behind the outside traces with exact waits; NIN = -1 reads p.nin and
+// loads the inputs in phase 3.
+template <typename real, int DIM, int N, int EQ, bool BUF, int SPOL, int YPOL, int TM, bool XIN = false,
+          int NIN = -1>
 __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
                                            StageLds<real, DIM, N, EQ, TM> &lds,
                                            const ThreadSetup<DIM, N, TM> &ts, real dval,
@@ -305,6 +317,7 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
     // blend of the six bases by masks (bitwise, so it stays in registers)
     auto outside_node = [nb0, nb1, nb2, nb3, nb4, nb5](uint32_t w0, uint32_t w2) -> idx_t {
         using U = typename std::make_unsigned<idx_t>::type;
+        (void)nb2, (void)nb3, (void)nb4, (void)nb5;     // unused below 3-D
         const uint32_t bsel = (w0 >> 3) & 7u;
         auto m = [bsel](uint32_t k) { return U(0) - U(bsel == k); };
         U b = (U(nb0) & m(0)) | (U(nb1) & m(1));
@@ -356,6 +369,21 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
 #pragma unroll
         for (int v = 0; v < NV; ++v) g2[v] = yin.ld(v, gn2);
     }
+    // RK inputs, issued last: the waits for the own state and the traces do
+    // not cover them
+    real a0[NV], a1[NV];
+    if constexpr (NIN >= 1) {
+        const A in0(p.in0, p.stride, NV);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) a0[v] = in0.template ld<SPOL>(v, gy);
+    }
+    if constexpr (NIN >= 2) {
+        const A in1(p.in1, p.stride, NV);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) a1[v] = in1.template ld<SPOL>(v, gy);
+    }
+    const bool has0 = NIN < 0 ? p.nin > 0 : NIN >= 1;
+    const bool has1 = NIN < 0 ? p.nin > 1 : NIN >= 2;
     // D (loaded at kernel entry into dval, stored here so the entry does not
     // wait for it before the tile's loads are issued)
     if (tid < N1 * N1) sD[tid] = dval;
@@ -486,19 +514,22 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
                 for (int v = 0; v < NV; ++v) R[v] += sL[v][li];
             }
         }
-        real a0[NV], a1[NV];
-        if (p.nin > 0) {
+        if (NIN < 0 && p.nin > 0) {
             const A in0(p.in0, p.stride, NV);
 #pragma unroll
             for (int v = 0; v < NV; ++v) a0[v] = in0.template ld<SPOL>(v, gi);
         }
-        if (p.nin > 1) {
+        if (NIN < 0 && p.nin > 1) {
             const A in1(p.in1, p.stride, NV);
 #pragma unroll
             for (int v = 0; v < NV; ++v) a1[v] = in1.template ld<SPOL>(v, gi);
         }
 #pragma unroll
         for (int o = 0; o < 2; ++o) {
+            // RK combination in one fixed rounding sequence, cy y, then fused
+            // multiply-adds of the inputs in order, R last, whatever the
+            // kernel variant knows about the inputs at compile time
+#pragma clang fp contract(off)
             if (o < p.nout) {
                 const real cy = real(p.cy[o]), c0 = real(p.c0[o]), c1 = real(p.c1[o]),
                            cr = real(p.cr[o]);
@@ -507,10 +538,9 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
                         real val = cy * y[v];
-                        if (p.nin > 0) val += c0 * a0[v];
-                        if (p.nin > 1) val += c1 * a1[v];
-                        val += cr * R[v];
-                        out.template st<SPOL>(v, gi, val);
+                        if (has0) val = fmadd(c0, a0[v], val);
+                        if (has1) val = fmadd(c1, a1[v], val);
+                        out.template st<SPOL>(v, gi, fmadd(cr, R[v], val));
                     }
                 } else {
                     // fused RK6 stages: also the stored k's with nonzero weights
@@ -518,25 +548,25 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
                         val[v] = cy * y[v];
-                        if (p.nin > 0) val[v] += c0 * a0[v];
-                        if (p.nin > 1) val[v] += c1 * a1[v];
+                        if (has0) val[v] = fmadd(c0, a0[v], val[v]);
+                        if (has1) val[v] = fmadd(c1, a1[v], val[v]);
                     }
                     for (int j = 0; j < x->n; ++j) {
                         if (x->c[o][j] == 0.0) continue;
                         const real cj = real(x->c[o][j]);
                         const A in(x->in[j], p.stride, NV);
 #pragma unroll
-                        for (int v = 0; v < NV; ++v) val[v] += cj * in.template ld<SPOL>(v, gi);
+                        for (int v = 0; v < NV; ++v) val[v] = fmadd(cj, in.template ld<SPOL>(v, gi), val[v]);
                     }
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) out.template st<SPOL>(v, gi, val[v] + cr * R[v]);
+                    for (int v = 0; v < NV; ++v) out.template st<SPOL>(v, gi, fmadd(cr, R[v], val[v]));
                 }
             }
         }
     }
 }
 
-template <typename real, int DIM, int N, int EQ, bool BUF, int SPOL = 0, int YPOL = 0, int TM = 1>
+template <typename real, int DIM, int N, int EQ, bool BUF, int NIN, int SPOL = 0, int YPOL = 0, int TM = 1>
 __global__ void __launch_bounds__((Geo<DIM, N, TM>::THREADS)) __attribute__((amdgpu_waves_per_eu(4)))
 stage_kernel(const StageParams p)
 {
@@ -548,7 +578,7 @@ stage_kernel(const StageParams p)
         // tile number: XCD-contiguous renumbering of the virtual block
         const uint32_t xb = vb & (kXcds - 1), jb = vb / kXcds;
         const uint32_t L = p.plain_order ? vb : xb * p.xq + (xb < p.xr ? xb : p.xr) + jb;
-        stage_tile<real, DIM, N, EQ, BUF, SPOL, YPOL, TM>(p, L, lds, ts, dval);
+        stage_tile<real, DIM, N, EQ, BUF, SPOL, YPOL, TM, false, NIN>(p, L, lds, ts, dval);
         __syncthreads();
     }
 }
@@ -574,7 +604,7 @@ stage_kernel_x(const StageParams p, const ExtraIn x)
 // precision, equation, dimension, degree; meshes, arrays and time steps
 // differ). Virtual tile T (XCD-contiguous numbering over all solves) belongs
 // to solve tile_solve[T] and is that solve's tile T - tile_base[solve].
-template <typename real, int DIM, int N, int EQ, bool BUF>
+template <typename real, int DIM, int N, int EQ, bool BUF, int NIN>
 __global__ void __launch_bounds__((Geo<DIM, N>::THREADS)) __attribute__((amdgpu_waves_per_eu(4)))
 stage_kernel_batch(const BatchLaunch b)
 {
@@ -586,33 +616,53 @@ stage_kernel_batch(const BatchLaunch b)
         const uint32_t xb = vb & (kXcds - 1), jb = vb / kXcds;
         const uint32_t T = xb * b.xq + (xb < b.xr ? xb : b.xr) + jb;
         const uint32_t s = b.tile_solve[T];
-        stage_tile<real, DIM, N, EQ, BUF, 0, 0, 1>(b.params[s], T - b.tile_base[s], lds, ts, dval);
+        stage_tile<real, DIM, N, EQ, BUF, 0, 0, 1, false, NIN>(b.params[s], T - b.tile_base[s], lds, ts, dval);
         __syncthreads();
+    }
+}
+
+template <typename real, int DIM, int N, int EQ, bool BUF>
+void launch_stage_nin(const StageParams &p, int64_t grid, hipStream_t s)
+{
+    const dim3 g((unsigned)grid), b(Geo<DIM, N>::THREADS);
+    switch (p.nin) {
+    case 0: hipLaunchKernelGGL((stage_kernel<real, DIM, N, EQ, BUF, 0>), g, b, 0, s, p); break;
+    case 1: hipLaunchKernelGGL((stage_kernel<real, DIM, N, EQ, BUF, 1>), g, b, 0, s, p); break;
+    default: hipLaunchKernelGGL((stage_kernel<real, DIM, N, EQ, BUF, 2>), g, b, 0, s, p); break;
     }
 }
 
 template <typename real, int DIM, int N, int EQ>
 hipError_t launch_stage(const StageParams &p, int64_t grid, hipStream_t s)
 {
+    if (p.nin < 0 || p.nin > 2) return hipErrorInvalidValue;
     const int64_t bytes = p.stride * Vars<EQ, DIM>::NV * (int64_t)sizeof(real);
     if (bytes < (int64_t(1) << 31))
-        hipLaunchKernelGGL((stage_kernel<real, DIM, N, EQ, true>), dim3((unsigned)grid),
-                           dim3(Geo<DIM, N>::THREADS), 0, s, p);
+        launch_stage_nin<real, DIM, N, EQ, true>(p, grid, s);
     else
-        hipLaunchKernelGGL((stage_kernel<real, DIM, N, EQ, false>), dim3((unsigned)grid),
-                           dim3(Geo<DIM, N>::THREADS), 0, s, p);
+        launch_stage_nin<real, DIM, N, EQ, false>(p, grid, s);
     return hipGetLastError();
 }
 
-template <typename real, int DIM, int N, int EQ>
-hipError_t launch_stage_batch(const BatchLaunch &b, bool buf, int64_t grid, hipStream_t s)
+template <typename real, int DIM, int N, int EQ, bool BUF>
+void launch_stage_batch_nin(const BatchLaunch &b, int nin, int64_t grid, hipStream_t s)
 {
+    const dim3 g((unsigned)grid), t(Geo<DIM, N>::THREADS);
+    switch (nin) {
+    case 0: hipLaunchKernelGGL((stage_kernel_batch<real, DIM, N, EQ, BUF, 0>), g, t, 0, s, b); break;
+    case 1: hipLaunchKernelGGL((stage_kernel_batch<real, DIM, N, EQ, BUF, 1>), g, t, 0, s, b); break;
+    default: hipLaunchKernelGGL((stage_kernel_batch<real, DIM, N, EQ, BUF, 2>), g, t, 0, s, b); break;
+    }
+}
+
+template <typename real, int DIM, int N, int EQ>
+hipError_t launch_stage_batch(const BatchLaunch &b, bool buf, int nin, int64_t grid, hipStream_t s)
+{
+    if (nin < 0 || nin > 2) return hipErrorInvalidValue;
     if (buf)
-        hipLaunchKernelGGL((stage_kernel_batch<real, DIM, N, EQ, true>), dim3((unsigned)grid),
-                           dim3(Geo<DIM, N>::THREADS), 0, s, b);
+        launch_stage_batch_nin<real, DIM, N, EQ, true>(b, nin, grid, s);
     else
-        hipLaunchKernelGGL((stage_kernel_batch<real, DIM, N, EQ, false>), dim3((unsigned)grid),
-                           dim3(Geo<DIM, N>::THREADS), 0, s, b);
+        launch_stage_batch_nin<real, DIM, N, EQ, false>(b, nin, grid, s);
     return hipGetLastError();
 }
 
