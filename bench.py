@@ -69,8 +69,9 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload: str, precision: str):
-    """Measured HBM bytes per stage launch from profiles/, if the kernel is unchanged."""
+def load_traffic(workload: str, precision: str, launch_cfg):
+    """Measured HBM bytes per stage launch from profiles/, if the kernel and the
+    launch configuration (tile order, z-slab, x-block) are those measured."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{precision}.json")
     if not os.path.exists(path):
         return None
@@ -79,6 +80,9 @@ def load_traffic(workload: str, precision: str):
     except (OSError, ValueError):
         return None
     if rec.get("kernel_hash") != kernel_hash():
+        return None
+    cfg = rec.get("launch_config")
+    if cfg is not None and list(cfg) != [launch_cfg[0], launch_cfg[1], launch_cfg[4]]:
         return None
     return rec.get("bytes_per_launch")
 
@@ -223,6 +227,8 @@ def main():
     ap.add_argument("--chunk", type=int, default=32)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--efficiency", action="store_true", help="error vs computing time study")
+    ap.add_argument("--launch-config", default=None, metavar="ORDER,SLAB,XBLOCK",
+                    help="tile order (0 XCD-contiguous, 1 plain), z-slab, x-block to time")
     ap.add_argument("--autotune", action="store_true",
                     help="autotune the launch configuration before timing (the committed traffic "
                          "counters are for the default configuration)")
@@ -257,6 +263,11 @@ def main():
     m0 = s.mass()
     # launch configuration: the default, or autotuned before the timed region
     # (every candidate computes the same results)
+    if a.launch_config:
+        order, slab, xblk = (int(x) for x in a.launch_config.split(","))
+        c = list(s.launch_config())
+        c[0], c[1], c[4] = order, slab, xblk
+        s.set_launch_config(c)
     launch_cfg = s.autotune(a.rk, dt, 3) if a.autotune else s.launch_config()
 
     s.step(a.rk, dt, a.warmup)
@@ -283,7 +294,7 @@ def main():
     avg_launch_s = ms / 1e3 / launches
     alg_bytes = PASSES_PER_STEP[a.rk] / stages * w.unknowns * rsize
     achieved = alg_bytes / avg_launch_s / 1e9
-    traffic = load_traffic(w.name, a.precision)
+    traffic = load_traffic(w.name, a.precision, launch_cfg)
 
     # achievable bandwidth: a plain device-to-device copy of 2 GiB
     src = torch.empty(1 << 28, dtype=torch.float64, device="cuda")
@@ -323,7 +334,7 @@ def main():
                      "avg_launch_us": avg_launch_s * 1e6},
         "launch_config": {"tile_order": "plain" if launch_cfg[0] else "xcd_contiguous",
                           "z_slab": launch_cfg[1], "halo_divisor_1d": launch_cfg[2],
-                          "autotuned": bool(launch_cfg[3])},
+                          "x_block": launch_cfg[4], "autotuned": bool(launch_cfg[3])},
         "nodes_per_s": w.nodes * stages * a.steps / (ms / 1e3),
         "copy_gbps": copy_gbs,
         "mass_drift": (np.abs(m1 - m0) / np.maximum(np.abs(m0), 1.0)).max(),

@@ -161,19 +161,32 @@ void *dg_stream(const dg_solver *h);
  * dt: times trial_steps (1..1000) steps of each candidate on the solver's
  * arrays, restarting from a saved copy of the state, restores the state and
  * keeps the fastest candidate for later dg_step calls. Candidates: 3-D, the
- * tile order (XCD-contiguous or plain) and the z-slab size; 2-D, the tile
- * order; 1-D RK3/RK4 meshes split into chunks, the steps per launch (via the
- * halo bound). Every candidate computes the same results bit for bit; only
- * speed differs. Synchronous. Needs a library-owned workspace (DG_ENOTSUP
- * otherwise: it allocates one state-sized copy); DG_ESTATE before the first
- * set_state or for a batch member. */
+ * tile order (XCD-contiguous or plain) x the z-slab size x the x-block
+ * width; 2-D, the tile order; 1-D RK3/RK4 meshes split into chunks, the
+ * steps per launch (via the halo bound). Every candidate computes the same
+ * results bit for bit; only speed differs. Synchronous. Needs a
+ * library-owned workspace (DG_ENOTSUP otherwise: it allocates one
+ * state-sized copy); DG_ESTATE before the first set_state or for a batch
+ * member. */
 int dg_autotune(dg_solver *h, int rk, double dt, int trial_steps);
 
 /* The launch configuration in use: cfg[0] tile order (0 XCD-contiguous,
- * 1 plain), cfg[1] z-slab size, cfg[2] 1-D halo-bound divisor (steps per
- * launch = capacity / (cfg[2] * stages)), cfg[3] 1 once autotuned. Writes
- * min(n, 4) entries and zeros beyond. */
+ * 1 plain), cfg[1] z-slab size (z-layers visited together), cfg[2] 1-D
+ * halo-bound divisor (steps per launch = capacity / (cfg[2] * stages)),
+ * cfg[3] 1 once autotuned, cfg[4] x-block width (x-tiles visited together;
+ * the number of x-tiles by default). Writes min(n, 5) entries and zeros
+ * beyond. */
 int dg_launch_config(const dg_solver *h, int64_t *cfg, int n);
+
+/* Set the launch configuration (same layout as dg_launch_config, n = 5;
+ * cfg[3] is ignored and the autotuned flag cleared), e.g. to reapply a
+ * configuration found by dg_autotune in an earlier run. 3-D: cfg[1] must
+ * divide K[2] and cfg[4] the number of x-tiles; 1-D/2-D: cfg[1] and cfg[4]
+ * must equal the values in use. cfg[0] in {0, 1}, cfg[2] in 1..1024. Every
+ * configuration computes the same results bit for bit. DG_EINVAL on a bad
+ * entry (nothing changed), DG_ESTATE for a batch member. Takes effect at the
+ * next dg_step; work already enqueued is unaffected. */
+int dg_set_launch_config(dg_solver *h, const int64_t *cfg, int n);
 
 /* ---------------------------------------------------------------------------
  * Batched stepping (many solves advanced together; the method per solve is

@@ -113,14 +113,18 @@ StageParams base_params(const dg_solver *h)
     p.stride = h->nodes;
     p.D = h->Dtab;
     p.tiles_x = h->tiles_x;
+    p.tiles_y = h->tiles_y;
     p.slab = h->slab;
+    p.xblk = h->xblk;
     p.ntiles = h->ntiles;
     p.ntiles32 = (uint32_t)h->ntiles;
     p.xq = (uint32_t)(h->ntiles / kXcds);
     p.xr = (uint32_t)(h->ntiles % kXcds);
     p.fd_tx = make_fastdiv((uint32_t)h->tiles_x);
     p.fd_slab = make_fastdiv((uint32_t)h->slab);
-    p.fd_k1 = make_fastdiv((uint32_t)h->K[1]);
+    p.fd_ty = make_fastdiv((uint32_t)h->tiles_y);
+    p.fd_xb = make_fastdiv((uint32_t)h->xblk);
+    p.fd_nslab = make_fastdiv((uint32_t)(h->K[2] / h->slab));
     p.ftab = h->ftab;
     p.plain_order = (uint32_t)h->plain_order;
     return p;
@@ -534,12 +538,15 @@ int dg_create_ex(int dim, int N, const int64_t *K, int equation, const double *p
     h->stage = fn;
     h->epb = stage_epb(dim, N);
     h->tiles_x = (h->K[0] + h->epb - 1) / h->epb;
+    h->epy = stage_epy(dim, N);
+    h->tiles_y = (h->K[1] + h->epy - 1) / h->epy;
     h->slab = 1;
     if (dim == 3) {
         for (int64_t s = std::max<int64_t>(1, h->K[2] / kXcds); s >= 1; --s)
             if (h->K[2] % s == 0) { h->slab = s; break; }
     }
-    h->ntiles = h->tiles_x * h->K[1] * h->K[2];
+    h->xblk = h->tiles_x;
+    h->ntiles = h->tiles_x * h->tiles_y * h->K[2];
     h->grid = std::min<int64_t>(h->ntiles, kMaxGrid);
 
     e = hipGetDevice(&h->device);
@@ -598,8 +605,8 @@ int dg_create_ex(int dim, int N, const int64_t *K, int equation, const double *p
         for (int i = 0; i < nd; ++i) f[i] = (float)h->D[i];
     }
     const size_t dbytes = (precision == DG_FP64 ? 8 : 4) * (size_t)nd;
-    std::vector<uint32_t> ftab(4 * (size_t)face_table_size(dim, N, h->epb));
-    build_face_table(dim, N, h->epb, ftab.data());
+    std::vector<uint32_t> ftab(4 * (size_t)face_table_size(dim, N, h->epb, h->epy));
+    build_face_table(dim, N, h->epb, h->epy, ftab.data());
     if (ftab.size() * 4 > kFaceTableBytes) {
         free_solver(h);
         return fail(DG_ENOTSUP, "face table larger than reserved");
@@ -801,19 +808,23 @@ int dg_autotune(dg_solver *h, int rk, double dt, int trial_steps)
     if (rc) return rc;
     if (rk == DG_RK6 && (rc = ensure_rk6(h))) return rc;
 
-    // candidate launch configurations (tile order, z-slab, 1-D halo bound)
-    struct Cfg { int plain, ms_div; int64_t slab; };
+    // candidate launch configurations (tile order, z-slab, x-block, 1-D halo bound)
+    struct Cfg { int plain, ms_div; int64_t slab, xblk; };
     std::vector<Cfg> cand;
     const bool ms = ms_plan(h, rk).ok;
     if (ms) {
         if (!ms_plan(h, rk).whole)
-            for (int dv : {3, 4, 6, 10, 16}) cand.push_back({h->plain_order, dv, h->slab});
+            for (int dv : {3, 4, 6, 10, 16}) cand.push_back({h->plain_order, dv, h->slab, h->xblk});
     } else if (h->dim == 3) {
+        // x-blocks: the whole row, then halvings down to 2 tiles
+        std::vector<int64_t> xbs{h->tiles_x};
+        for (int64_t xb = h->tiles_x; xb % 2 == 0 && xb / 2 >= 2; xb /= 2) xbs.push_back(xb / 2);
         for (int plain = 0; plain <= 1; ++plain)
             for (int64_t sl = 1; sl <= h->K[2]; sl *= 2)
-                if (h->K[2] % sl == 0) cand.push_back({plain, h->ms_div, sl});
+                if (h->K[2] % sl == 0)
+                    for (int64_t xb : xbs) cand.push_back({plain, h->ms_div, sl, xb});
     } else {
-        for (int plain = 0; plain <= 1; ++plain) cand.push_back({plain, h->ms_div, h->slab});
+        for (int plain = 0; plain <= 1; ++plain) cand.push_back({plain, h->ms_div, h->slab, h->xblk});
     }
     if (cand.size() < 2) {
         h->tuned = 1;
@@ -831,7 +842,7 @@ int dg_autotune(dg_solver *h, int rk, double dt, int trial_steps)
     rc = DG_OK;
     Cfg best = cand[0];
     float best_ms = -1.0f;
-    const Cfg keep = {h->plain_order, h->ms_div, h->slab};
+    const Cfg keep = {h->plain_order, h->ms_div, h->slab, h->xblk};
     e = hipMemcpyAsync(save, h->U, h->lay.array, hipMemcpyDeviceToDevice, h->stream);
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
@@ -839,6 +850,7 @@ int dg_autotune(dg_solver *h, int rk, double dt, int trial_steps)
         h->plain_order = cand[i].plain;
         h->ms_div = cand[i].ms_div;
         h->slab = cand[i].slab;
+        h->xblk = cand[i].xblk;
         rc = dg_step(h, rk, dt, 1);                                   // warm-up
         if (rc) break;
         e = hipMemcpyAsync(h->U, save, h->lay.array, hipMemcpyDeviceToDevice, h->stream);
@@ -864,6 +876,7 @@ int dg_autotune(dg_solver *h, int rk, double dt, int trial_steps)
     h->plain_order = use.plain;
     h->ms_div = use.ms_div;
     h->slab = use.slab;
+    h->xblk = use.xblk;
     if (rc) return rc;
     if (e != hipSuccess) return hip_fail(e, "autotuning");
     h->tuned = 1;
@@ -873,9 +886,32 @@ int dg_autotune(dg_solver *h, int rk, double dt, int trial_steps)
 int dg_launch_config(const dg_solver *h, int64_t *cfg, int n)
 {
     if (!h || !cfg || n < 0) return fail(DG_EINVAL, "NULL argument or n < 0");
-    const int64_t v[4] = {h->plain_order, h->slab, h->ms_div, h->tuned};
-    for (int i = 0; i < n && i < 4; ++i) cfg[i] = v[i];
-    for (int i = 4; i < n; ++i) cfg[i] = 0;
+    const int64_t v[kLaunchCfg] = {h->plain_order, h->slab, h->ms_div, h->tuned, h->xblk};
+    for (int i = 0; i < n && i < kLaunchCfg; ++i) cfg[i] = v[i];
+    for (int i = kLaunchCfg; i < n; ++i) cfg[i] = 0;
+    return DG_OK;
+}
+
+int dg_set_launch_config(dg_solver *h, const int64_t *cfg, int n)
+{
+    if (!h || !cfg) return fail(DG_EINVAL, "NULL argument");
+    if (n != kLaunchCfg) return fail(DG_EINVAL, "n must be 5");
+    if (h->batch) return fail(DG_ESTATE, "solver belongs to a batch");
+    const int64_t plain = cfg[0], slab = cfg[1], ms_div = cfg[2], xblk = cfg[4];
+    if (plain != 0 && plain != 1) return fail(DG_EINVAL, "cfg[0] (tile order) must be 0 or 1");
+    if (ms_div < 1 || ms_div > 1024) return fail(DG_EINVAL, "cfg[2] (halo-bound divisor) must be in 1..1024");
+    if (h->dim == 3) {
+        if (slab < 1 || h->K[2] % slab != 0) return fail(DG_EINVAL, "cfg[1] (z-slab) must divide K[2]");
+        if (xblk < 1 || h->tiles_x % xblk != 0)
+            return fail(DG_EINVAL, "cfg[4] (x-block) must divide the number of x-tiles");
+    } else if (slab != h->slab || xblk != h->xblk) {
+        return fail(DG_EINVAL, "z-slab and x-block apply to 3-D meshes only (pass the values in use)");
+    }
+    h->plain_order = (int)plain;
+    h->slab = slab;
+    h->ms_div = (int)ms_div;
+    h->xblk = xblk;
+    h->tuned = 0;
     return DG_OK;
 }
 

@@ -19,8 +19,8 @@ constexpr size_t kFaceTableBytes = 16384;
 void lgl_operator(int N, double *xi, double *w, double *D);
 
 // Face-point descriptor table of a workgroup tile (4 uint32 per face point).
-int face_table_size(int dim, int N, int epb);
-void build_face_table(int dim, int N, int epb, uint32_t *tab);
+int face_table_size(int dim, int N, int epb, int epy);
+void build_face_table(int dim, int N, int epb, int epy, uint32_t *tab);
 
 // Device workspace of one solver: tables, then the RK arrays.
 struct Layout {
@@ -42,6 +42,9 @@ size_t round_up(size_t x);
     } while (0)
 
 }  // namespace dg
+
+// entries of a launch configuration (dg_launch_config / dg_set_launch_config)
+constexpr int kLaunchCfg = 5;
 
 struct dg_solver {
     int dim = 0, N = 0, eq = 0, prec = 0, nvar = 0, n1 = 0, np = 0;
@@ -65,8 +68,8 @@ struct dg_solver {
     char *rk6_mem = nullptr;        // library-owned RK6 extension
     bool has_state = false;
     dg::StageFn stage = nullptr;
-    int epb = 0;
-    int64_t tiles_x = 0, slab = 1, ntiles = 0, grid = 0;
+    int epb = 0, epy = 1;
+    int64_t tiles_x = 0, tiles_y = 1, slab = 1, xblk = 1, ntiles = 0, grid = 0;
     // launch configuration (dg_autotune may change it; results do not depend
     // on it): tile order 0 XCD-contiguous / 1 plain; 1-D steps per launch
     // follow from the halo bound capacity / (ms_div * stages)

@@ -58,15 +58,18 @@ struct StageParams {
     double par[3];         // advection a_d, or {c_s} for isothermal Euler
     const void *D;         // (N+1)^2 differentiation matrix, row-major, in the
                            // state's precision: D[i*(N+1)+m] = h_m'(xi_i)
-    int64_t tiles_x;       // ceil(K[0] / elements-per-block)
+    int64_t tiles_x;       // ceil(K[0] / elements per tile along x)
+    int64_t tiles_y;       // ceil(K[1] / element rows per tile)
     int64_t slab;          // 3-D: z-layers per XCD slab (divides K[2])
+    int64_t xblk;          // 3-D: x-tiles per x-block (divides tiles_x)
     int64_t ntiles;        // number of element tiles (virtual blocks)
     // 32-bit tile decoding: virtual block b runs on XCD b % 8; tiles are
     // renumbered L = x * xq + min(x, xr) + b / 8 so each XCD owns a contiguous
-    // range, then L -> (x-tile, z in slab, y, slab) by the divisions below.
+    // range, then L -> (x-tile, y-tile) in 2-D and (x-tile in x-block, z in
+    // slab, y-tile, slab, x-block) in 3-D by the divisions below.
     uint32_t ntiles32, xq, xr;
     uint32_t plain_order;  // 1: tile L = virtual block (no XCD renumbering)
-    FastDiv fd_tx, fd_slab, fd_k1;
+    FastDiv fd_tx, fd_slab, fd_ty, fd_xb, fd_nslab;
     const uint32_t *ftab;  // face-point descriptors of a tile (dg_tables.cpp)
 };
 
@@ -161,6 +164,7 @@ BatchFn batch_fn(int precision, int equation, int dim, int N);
 // Threads per block and elements per block of the stage kernel for (dim, N).
 int stage_threads(int dim, int N);
 int stage_epb(int dim, int N);
+int stage_epy(int dim, int N);
 
 hipError_t launch_reduce(int precision, const ReduceParams &p, int64_t blocks, hipStream_t s);
 hipError_t launch_cast(int to_precision, int from_precision, const CastParams &p, hipStream_t s);

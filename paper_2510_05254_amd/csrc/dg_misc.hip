@@ -111,12 +111,13 @@ StageFn stage_fn(int precision, int equation, int dim, int N)
     return table[precision][dim - 1][equation](N);
 }
 
+// what: 0 threads per workgroup, 1 elements per tile along x, 2 element rows
 template <int DIM>
-static int threads_n(int N, bool epb)
+static int threads_n(int N, int what)
 {
     switch (N) {
 #define DG_CASE(n) \
-    case n: return epb ? Geo<DIM, n>::EPB : Geo<DIM, n>::THREADS;
+    case n: return what == 0 ? Geo<DIM, n>::THREADS : what == 1 ? Geo<DIM, n>::EPB : Geo<DIM, n>::EPY;
         DG_CASE(1) DG_CASE(2) DG_CASE(3) DG_CASE(4) DG_CASE(5) DG_CASE(6) DG_CASE(7) DG_CASE(8)
 #undef DG_CASE
     default: return 0;
@@ -125,12 +126,17 @@ static int threads_n(int N, bool epb)
 
 int stage_threads(int dim, int N)
 {
-    return dim == 1 ? threads_n<1>(N, false) : dim == 2 ? threads_n<2>(N, false) : threads_n<3>(N, false);
+    return dim == 1 ? threads_n<1>(N, 0) : dim == 2 ? threads_n<2>(N, 0) : threads_n<3>(N, 0);
 }
 
 int stage_epb(int dim, int N)
 {
-    return dim == 1 ? threads_n<1>(N, true) : dim == 2 ? threads_n<2>(N, true) : threads_n<3>(N, true);
+    return dim == 1 ? threads_n<1>(N, 1) : dim == 2 ? threads_n<2>(N, 1) : threads_n<3>(N, 1);
+}
+
+int stage_epy(int dim, int N)
+{
+    return dim == 1 ? threads_n<1>(N, 2) : dim == 2 ? threads_n<2>(N, 2) : threads_n<3>(N, 2);
 }
 
 static int64_t grid_for(int64_t n, int threads)

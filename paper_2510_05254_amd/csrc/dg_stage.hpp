@@ -17,7 +17,8 @@
 //
 // Work decomposition (MI355X-specific, not from the paper). A workgroup owns
 // a tile of EPB consecutive elements along x (EPB * (N+1)^dim nodes, ~256
-// threads) and runs three phases separated by barriers:
+// threads), times two rows along y for 3-D N = 4 (512 threads), and runs
+// three phases separated by barriers:
 //  1. node-parallel: load the stage input (one thread per node, variables in
 //     registers), stage it in LDS together with 1/rho and the symmetric
 //     momentum-flux tensor m_a m_b / rho + delta_ab rho c^2;
@@ -38,8 +39,10 @@
 //
 // Tile order: virtual block b runs on XCD b % 8 (private L2 per XCD); tiles
 // are renumbered so each XCD owns a contiguous range, in the order x-tile
-// fastest, then z inside a slab of `slab` layers, then y, then slab, which
-// keeps the y- and z-neighbours of a tile among recently visited tiles.
+// fastest within an x-block of `xblk` tiles, then z inside a slab of `slab`
+// layers, then y, then slab, then x-block, which keeps the y- and
+// z-neighbours of a tile among recently visited tiles (xblk slab and xblk
+// tiles back).
 #pragma once
 
 #include <type_traits>
@@ -50,19 +53,29 @@ namespace dg {
 
 constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 
-// TM scales the tile: EPB = max(1, 256 TM / (N+1)^dim) elements per workgroup
+// Rows of elements along y per tile: two for 3-D N = 4, whose tile of 2 x 2
+// elements (512 threads) reads half the y-face traces per element of a 2 x 1
+// tile and has its 500 face points in one pass.
+constexpr int tile_rows(int DIM, int N) { return DIM == 3 && N == 4 ? 2 : 1; }
+
+// A tile is EPB elements along x times EPY along y; TM scales it along x:
+// EPB = max(1, 256 TM / (N+1)^dim).
 template <int DIM, int N, int TM = 1>
 struct Geo {
     static constexpr int N1 = N + 1;
     static constexpr int NP = ipow(N1, DIM);          // nodes per element
     static constexpr int NF1 = ipow(N1, DIM - 1);     // nodes per face
     static constexpr int EPB = (256 * TM / NP) < 1 ? 1 : (256 * TM / NP);
-    static constexpr int TN = EPB * NP;
+    static constexpr int EPY = tile_rows(DIM, N);
+    static_assert(EPY == 1 || EPY == 2, "the face table encodes one bit of tile row");
+    static constexpr int NS = EPB * EPY;              // element slots, slot = sx + EPB sy
+    static constexpr int TN = NS * NP;
     static constexpr int THREADS = ((TN + 63) / 64) * 64;
-    static constexpr int NFX = (EPB + 1) * NF1;       // x-face points of a tile
-    static constexpr int NFO = EPB * 2 * NF1;         // face points per other direction
-    static constexpr int NF = NFX + (DIM - 1) * NFO;
-    static constexpr int NL = DIM * EPB * 2 * NF1;    // lift slots per variable
+    static constexpr int NFX = EPY * (EPB + 1) * NF1;                 // x-plane points
+    static constexpr int NFY = DIM > 1 ? EPB * (EPY + 1) * NF1 : 0;   // y-plane points
+    static constexpr int NFZ = DIM > 2 ? NS * 2 * NF1 : 0;            // z-face points
+    static constexpr int NF = NFX + NFY + NFZ;
+    static constexpr int NL = DIM * NS * 2 * NF1;     // lift slots per variable
 };
 
 template <int EQ, int DIM>
@@ -220,12 +233,14 @@ struct StageLds {
 // per-thread constants of a workgroup (independent of the tile)
 template <int DIM, int N, int TM>
 struct ThreadSetup {
-    int tid, slot, n, ijk[3];
+    int tid, slot, sx, sy, n, ijk[3];
     __device__ __forceinline__ ThreadSetup()
     {
         using G = Geo<DIM, N, TM>;
         tid = threadIdx.x;
         slot = tid / G::NP;
+        sy = slot / G::EPB;
+        sx = slot - sy * G::EPB;
         n = tid - slot * G::NP;
         ijk[0] = n % G::N1;
         ijk[1] = DIM > 1 ? (n / G::N1) % G::N1 : 0;
@@ -233,7 +248,7 @@ struct ThreadSetup {
     }
 };
 
-// One tile (EPB consecutive elements along x) of one RHS + RK stage: tile L of
+// One tile (EPB x EPY elements) of one RHS + RK stage: tile L of
 // the solve described by p, in that solve's tile numbering. NIN >= 0 fixes the
 // number of RK inputs (p.nin) at compile time, so their loads are issued in
 // phase 1 behind the outside traces with exact waits; NIN = -1 reads p.nin and
@@ -246,7 +261,7 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
                                            const ExtraIn *x = nullptr)
 {
     using G = Geo<DIM, N, TM>;
-    constexpr int N1 = G::N1, NP = G::NP, NF1 = G::NF1, EPB = G::EPB;
+    constexpr int N1 = G::N1, NP = G::NP, NF1 = G::NF1, EPB = G::EPB, EPY = G::EPY, NS = G::NS;
     constexpr int THREADS = G::THREADS, NF = G::NF;
     constexpr int NV = Vars<EQ, DIM>::NV;
     constexpr real INVW0 = real(N * (N + 1)) / real(2);     // 1/w_0 = 1/w_N
@@ -270,67 +285,78 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
     const real c2 = par[0] * par[0];
     const int64_t K0 = p.K[0], K1 = p.K[1], K2 = p.K[2];
 
-    int64_t tx, ey, ez;
+    int64_t tx, ty, ez;
     if constexpr (DIM == 1) {
-        tx = L; ey = 0; ez = 0;
+        tx = L; ty = 0; ez = 0;
     } else if constexpr (DIM == 2) {
         const uint32_t r1 = fast_div(L, p.fd_tx);
-        tx = L - r1 * p.fd_tx.div; ey = r1; ez = 0;
+        tx = L - r1 * p.fd_tx.div; ty = r1; ez = 0;
     } else {
-        const uint32_t r1 = fast_div(L, p.fd_tx);
+        const uint32_t r1 = fast_div(L, p.fd_xb);
         const uint32_t r2 = fast_div(r1, p.fd_slab);
-        const uint32_t r3 = fast_div(r2, p.fd_k1);
-        tx = L - r1 * p.fd_tx.div;
+        const uint32_t r3 = fast_div(r2, p.fd_ty);
+        const uint32_t r4 = fast_div(r3, p.fd_nslab);
+        const uint32_t xi = L - r1 * p.fd_xb.div;
         const uint32_t zs = r1 - r2 * p.fd_slab.div;
-        ey = r2 - r3 * p.fd_k1.div;
-        ez = int64_t(r3) * p.fd_slab.div + zs;
+        ty = r2 - r3 * p.fd_ty.div;
+        ez = int64_t(r3 - r4 * p.fd_nslab.div) * p.fd_slab.div + zs;
+        tx = int64_t(r4) * p.fd_xb.div + xi;
     }
-    const int64_t ex0 = tx * EPB;
-    const int nact = (int)((K0 - ex0) < EPB ? (K0 - ex0) : EPB);
-    const int64_t ebase = K0 * (ey + K1 * ez);     // element index of (0, ey, ez)
+    const int64_t ex0 = tx * EPB, ey0 = ty * EPY;
+    const int nact = (int)((K0 - ex0) < EPB ? (K0 - ex0) : EPB);      // active x slots
+    const int nacty = (int)((K1 - ey0) < EPY ? (K1 - ey0) : EPY);     // active rows
+    const int64_t ebase = K0 * (ey0 + K1 * ez);    // element index of (0, ey0, ez)
 
     // Neighbour element bases (node offsets) of this tile, uniform: bsel =
     // 2 d + 1 for the upper neighbour along d, 2 d for the lower one (x: the
-    // elements left of the tile and right of its last active slot; y, z: the
-    // row of elements above/below the tile).
+    // elements left of the tile's first slot and right of its last active
+    // slot in row 0; y: the rows below the tile and above its last active
+    // row; z: the layers below/above the tile, at its first element). Faces
+    // of tile row sy add sy rows (rstride nodes) to an x or z base.
     auto wrap = [](int64_t e, int64_t K) { return e < 0 ? e + K : (e >= K ? e - K : e); };
     // named values, not an array: a select over array elements becomes a
     // dynamically indexed (scratch) load
     const idx_t nb0 = idx_t((ebase + wrap(ex0 - 1, K0)) * NP);
     const idx_t nb1 = idx_t((ebase + wrap(ex0 + nact, K0)) * NP);
+    const idx_t rstride = idx_t(K0 * NP);
     idx_t nb2 = 0, nb3 = 0, nb4 = 0, nb5 = 0;
     if constexpr (DIM > 1) {
-        nb2 = idx_t((ex0 + K0 * (wrap(ey - 1, K1) + K1 * ez)) * NP);
-        nb3 = idx_t((ex0 + K0 * (wrap(ey + 1, K1) + K1 * ez)) * NP);
+        nb2 = idx_t((ex0 + K0 * (wrap(ey0 - 1, K1) + K1 * ez)) * NP);
+        nb3 = idx_t((ex0 + K0 * (wrap(ey0 + nacty, K1) + K1 * ez)) * NP);
     }
     if constexpr (DIM > 2) {
-        nb4 = idx_t((ex0 + K0 * (ey + K1 * wrap(ez - 1, K2))) * NP);
-        nb5 = idx_t((ex0 + K0 * (ey + K1 * wrap(ez + 1, K2))) * NP);
+        nb4 = idx_t((ex0 + K0 * (ey0 + K1 * wrap(ez - 1, K2))) * NP);
+        nb5 = idx_t((ex0 + K0 * (ey0 + K1 * wrap(ez + 1, K2))) * NP);
     }
     // Face point fields (see dg_tables.cpp): w0 = d | other_is_lower << 2 |
-    // bsel << 3 | other_in_tile << 6 | need << 8 | xplane << 16,
-    // w1 = own_q | other_q << 16, w2 = outside node offset, w3 = lift slots.
-    auto face_valid = [nact](uint32_t w0) { return ((w0 >> 8) & 0xffu) <= uint32_t(nact); };
-    auto other_outside = [nact](uint32_t w0) {
-        return ((w0 >> 6) & 1u) == 0 || ((w0 >> 16) & 0xffu) == uint32_t(nact);
+    // bsel << 3 | other_in_tile << 6 | row << 7 | need << 8 | xplane << 16 |
+    // needy << 24 | yplane << 28, w1 = own_q | other_q << 16, w2 = outside
+    // node offset, w3 = lift slots.
+    auto face_valid = [nact, nacty](uint32_t w0) {
+        return ((w0 >> 8) & 0xffu) <= uint32_t(nact) && ((w0 >> 24) & 0xfu) <= uint32_t(nacty);
+    };
+    auto other_outside = [nact, nacty](uint32_t w0) {
+        return ((w0 >> 6) & 1u) == 0 || ((w0 >> 16) & 0xffu) == uint32_t(nact) ||
+               (w0 >> 28) == uint32_t(nacty);
     };
     // blend of the six bases by masks (bitwise, so it stays in registers)
-    auto outside_node = [nb0, nb1, nb2, nb3, nb4, nb5](uint32_t w0, uint32_t w2) -> idx_t {
+    auto outside_node = [nb0, nb1, nb2, nb3, nb4, nb5, rstride](uint32_t w0, uint32_t w2) -> idx_t {
         using U = typename std::make_unsigned<idx_t>::type;
-        (void)nb2, (void)nb3, (void)nb4, (void)nb5;     // unused below 3-D
+        (void)nb2, (void)nb3, (void)nb4, (void)nb5, (void)rstride;     // unused in 1-D
         const uint32_t bsel = (w0 >> 3) & 7u;
         auto m = [bsel](uint32_t k) { return U(0) - U(bsel == k); };
         U b = (U(nb0) & m(0)) | (U(nb1) & m(1));
         if constexpr (DIM > 1) b |= (U(nb2) & m(2)) | (U(nb3) & m(3));
         if constexpr (DIM > 2) b |= (U(nb4) & m(4)) | (U(nb5) & m(5));
+        if constexpr (EPY > 1) b += U(rstride) & (U(0) - U((w0 >> 7) & 1u));
         return idx_t(b) + idx_t(w2);
     };
 
     // ---- phase 1: state, 1/rho and flux tensor into LDS; the outside trace
     // of this thread's first face point is prefetched behind the own state.
-    const bool active = slot < nact;
+    const bool active = ts.sx < nact && ts.sy < nacty;
     const int ln = slot * NP + n;
-    const idx_t gi = idx_t((ebase + ex0 + slot) * NP + n);
+    const idx_t gi = idx_t((ebase + K0 * ts.sy + ex0 + ts.sx) * NP + n);
     // both groups are loaded unconditionally (inactive lanes read node 0) so
     // the wait before the LDS stores covers only the first group
     // Issue order matters (vector loads retire in order): this thread's first
@@ -509,7 +535,7 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
             if (id == 0 || id == N) {
                 const int t = d == 0 ? (DIM > 1 ? ijk[1] + N1 * ijk[2] : 0)
                                      : (d == 1 ? ijk[0] + N1 * ijk[2] : ijk[0] + N1 * ijk[1]);
-                const int li = ((d * EPB + slot) * 2 + (id == N ? 1 : 0)) * NF1 + t;
+                const int li = ((d * NS + slot) * 2 + (id == N ? 1 : 0)) * NF1 + t;
 #pragma unroll
                 for (int v = 0; v < NV; ++v) R[v] += sL[v][li];
             }

@@ -1,26 +1,33 @@
 // dg_tables.cpp -- host-built descriptor table of the face points of one
-// workgroup tile (EPB elements along x), used by the stage kernel's
-// face-parallel Lax-Friedrichs phase. The table depends only on (dim, N, EPB).
+// workgroup tile (EPB elements along x times EPY rows along y; slot
+// s = sx + EPB sy), used by the stage kernel's face-parallel Lax-Friedrichs
+// phase. The table depends only on (dim, N, EPB, EPY): offsets that depend on
+// the mesh (a row of elements) are applied in the kernel.
 //
-// Face point f of a tile, f in [0, NF):
-//   f <  NFX: x-plane pl = f / NF1 (0..EPB) at tangential node t = f % NF1,
-//             between slot pl-1 (its x-upper face) and slot pl (x-lower face);
-//             slot -1 / EPB are the neighbouring tiles (global memory);
-//   f >= NFX: direction d = 1, 2: the lower (side 0) or upper (side 1) face of
-//             slot s at tangential node t; the other side is the neighbouring
-//             element along d (global memory).
+// Face points, in table order (t: tangential node of the face):
+//   x-planes: row sy, plane pl = 0..EPB, t; plane pl lies between slot
+//             (pl-1, sy) (its x-upper face) and slot (pl, sy) (x-lower face);
+//             slots -1 / EPB are the neighbouring tiles (global memory);
+//   y-planes: column sx, plane py = 0..EPY, t; between rows py-1 and py of
+//             the column, rows -1 / EPY in the neighbouring tiles;
+//   z-faces:  slot, side (0 lower, 1 upper), t; the other side is always the
+//             neighbouring element along z (global memory).
 // Each face point has an "own" side inside the tile and an "other" side
-// (inside the tile only for x-planes between two tile slots). Entry (4 x uint32):
-//   w0 = d | other_is_lower << 2 | bsel << 3 | other_in_tile << 6 | need << 8 | xplane << 16
-//        need:   the point is active iff need <= nact, the tile's active slots
-//                (x-plane pl: need = pl; face of slot s: need = s + 1);
-//        xplane: pl for x-planes, 0xff otherwise; the other side of plane nact
-//                of a ragged tile lies outside the tile;
-//        bsel:   which neighbour element base holds an outside other side:
-//                2 d + (1 if that element is the upper neighbour);
+// (inside the tile only for planes between two tile slots). Entry (4 x uint32):
+//   w0 = d | other_is_lower << 2 | bsel << 3 | other_in_tile << 6 | row << 7 |
+//        need << 8 | xplane << 16 | needy << 24 | yplane << 28
+//        need, needy: the point is active iff need <= nact and needy <= nacty,
+//                the tile's active x slots and rows;
+//        xplane, yplane: pl / py of an in-tile plane (0xff / 0xf otherwise):
+//                the other side of plane nact (nacty) of a ragged tile lies
+//                outside the tile;
+//        bsel:   which neighbour base holds an outside other side:
+//                2 d + (1 if it is the upper neighbour);
+//        row:    the outside element lies in tile row 1 (x and z faces): one
+//                row of elements further than the base (so EPY <= 2);
 //   w1 = own_q | other_q << 16   tile node index (slot * Np + node) of each side
 //   w2 = goff                    node offset of an outside other side from its
-//                                neighbour base (x: node; y/z: s * Np + node)
+//                                base (x: node; y, z: sx * Np + node)
 //   w3 = own_lift | other_lift << 16   lift slots of the two sides
 #include <cstdint>
 #include <vector>
@@ -31,69 +38,127 @@ namespace dg {
 
 static int ipow_h(int b, int e) { return e == 0 ? 1 : b * ipow_h(b, e - 1); }
 
-int face_table_size(int dim, int N, int epb)
+int face_table_size(int dim, int N, int epb, int epy)
 {
     const int nf1 = ipow_h(N + 1, dim - 1);
-    return (epb + 1) * nf1 + (dim - 1) * epb * 2 * nf1;
+    const int nfx = epy * (epb + 1) * nf1;
+    const int nfy = dim > 1 ? epb * (epy + 1) * nf1 : 0;
+    const int nfz = dim > 2 ? epb * epy * 2 * nf1 : 0;
+    return nfx + nfy + nfz;
 }
 
-void build_face_table(int dim, int N, int epb, uint32_t *tab)
+namespace {
+
+struct FacePoint {
+    uint32_t d = 0, oth_lower = 0, bsel = 0, in_tile = 0, row = 0;
+    uint32_t need = 0, xplane = 0xff, needy = 1, yplane = 0xf;
+    uint32_t own_q = 0, oth_q = 0, goff = 0, own_lift = 0, oth_lift = 0xffff;
+};
+
+void put(const FacePoint &p, uint32_t *e)
+{
+    e[0] = p.d | p.oth_lower << 2 | p.bsel << 3 | p.in_tile << 6 | p.row << 7 | p.need << 8 |
+           p.xplane << 16 | p.needy << 24 | p.yplane << 28;
+    e[1] = p.own_q | p.oth_q << 16;
+    e[2] = p.goff;
+    e[3] = p.own_lift | p.oth_lift << 16;
+}
+
+}  // namespace
+
+void build_face_table(int dim, int N, int epb, int epy, uint32_t *tab)
 {
     const int N1 = N + 1, NF1 = ipow_h(N1, dim - 1);
-    const int NFX = (epb + 1) * NF1, NFO = epb * 2 * NF1;
-    const int NF = face_table_size(dim, N, epb);
-    auto lift = [&](int d, int slot, int side, int t) {
-        return (uint32_t)(((d * epb + slot) * 2 + side) * NF1 + t);
+    const uint32_t NP = (uint32_t)ipow_h(N1, dim);
+    const int ns = epb * epy;
+    auto slot = [&](int sx, int sy) { return (uint32_t)(sx + epb * sy); };
+    auto lift = [&](int d, uint32_t s, int side, int t) {
+        return (uint32_t)(((d * ns + (int)s) * 2 + side) * NF1 + t);
     };
-    for (int f = 0; f < NF; ++f) {
-        uint32_t d, kind, ps, own_node, oth_node, own_lift, oth_lift = 0xffff, oth_lower;
-        int own_slot, oth_slot;
-        if (f < NFX) {
-            const int pl = f / NF1, t = f % NF1;
-            d = 0; kind = 0; ps = (uint32_t)pl;
-            const uint32_t lnode = (uint32_t)(N + N1 * t), rnode = (uint32_t)(N1 * t);
-            if (pl == 0) {            // own: slot 0 (upper side), other: tile to the left
-                own_slot = 0; own_node = rnode; own_lift = lift(0, 0, 0, t);
-                oth_slot = -1; oth_node = lnode; oth_lower = 1;
-            } else {                  // own: slot pl-1 (lower side), other: slot pl or outside
-                own_slot = pl - 1; own_node = lnode; own_lift = lift(0, pl - 1, 1, t);
-                oth_node = rnode; oth_lower = 0;
-                oth_slot = pl < epb ? pl : -1;
-                if (oth_slot >= 0) oth_lift = lift(0, pl, 0, t);
+    uint32_t *e = tab;
+    // x-planes; face node t = j + N1 k, lower side at i = N, upper side at i = 0
+    for (int sy = 0; sy < epy; ++sy)
+        for (int pl = 0; pl <= epb; ++pl)
+            for (int t = 0; t < NF1; ++t, e += 4) {
+                const uint32_t lnode = (uint32_t)(N + N1 * t), rnode = (uint32_t)(N1 * t);
+                FacePoint p;
+                p.d = 0;
+                p.need = (uint32_t)pl;
+                p.needy = (uint32_t)(sy + 1);
+                p.xplane = (uint32_t)pl;
+                p.row = (uint32_t)sy;
+                if (pl == 0) {        // own: slot (0, sy) (upper side), other: tile to the left
+                    p.own_q = slot(0, sy) * NP + rnode;
+                    p.own_lift = lift(0, slot(0, sy), 0, t);
+                    p.oth_lower = 1;
+                    p.bsel = 0;
+                    p.goff = lnode;
+                } else {              // own: slot (pl-1, sy) (lower side), other: slot (pl, sy) or outside
+                    p.own_q = slot(pl - 1, sy) * NP + lnode;
+                    p.own_lift = lift(0, slot(pl - 1, sy), 1, t);
+                    p.oth_lower = 0;
+                    p.bsel = 1;
+                    p.goff = rnode;
+                    if (pl < epb) {
+                        p.in_tile = 1;
+                        p.oth_q = slot(pl, sy) * NP + rnode;
+                        p.oth_lift = lift(0, slot(pl, sy), 0, t);
+                    }
+                }
+                put(p, e);
             }
-        } else {
-            const int g = f - NFX;
-            d = (uint32_t)(1 + g / NFO);
-            const int r = g % NFO;
-            const int s = r / (2 * NF1), side = (r / NF1) % 2, t = r % NF1;
-            const int ta = t % N1, tb = t / N1;
-            const uint32_t nlo = d == 1 ? (uint32_t)(ta + N1 * (0 + N1 * tb)) : (uint32_t)(ta + N1 * (tb + N1 * 0));
-            const uint32_t nhi = d == 1 ? (uint32_t)(ta + N1 * (N + N1 * tb)) : (uint32_t)(ta + N1 * (tb + N1 * N));
-            ps = (uint32_t)s;
-            own_slot = s;
-            oth_slot = -1;
-            if (side == 0) {          // lower face: own is the upper side of the face
-                kind = 1; own_node = nlo; oth_node = nhi; oth_lower = 1;
-                own_lift = lift((int)d, s, 0, t);
-            } else {                  // upper face: own is the lower side of the face
-                kind = 2; own_node = nhi; oth_node = nlo; oth_lower = 0;
-                own_lift = lift((int)d, s, 1, t);
-            }
-        }
-        const uint32_t NP = (uint32_t)ipow_h(N1, dim);
-        const uint32_t in_tile = oth_slot >= 0 ? 1u : 0u;
-        const uint32_t upper_nb = oth_lower ? 0u : 1u;
-        const uint32_t bsel = 2 * d + upper_nb;
-        const uint32_t need = kind == 0 ? ps : ps + 1;
-        const uint32_t xplane = kind == 0 ? ps : 0xffu;
-        const uint32_t own_q = (uint32_t)own_slot * NP + own_node;
-        const uint32_t oth_q = in_tile ? (uint32_t)oth_slot * NP + oth_node : 0u;
-        const uint32_t goff = kind == 0 ? oth_node : ps * NP + oth_node;
-        tab[4 * f + 0] = d | oth_lower << 2 | bsel << 3 | in_tile << 6 | need << 8 | xplane << 16;
-        tab[4 * f + 1] = own_q | oth_q << 16;
-        tab[4 * f + 2] = goff;
-        tab[4 * f + 3] = own_lift | oth_lift << 16;
-    }
+    // y-planes; face node t = i + N1 k, lower side at j = N, upper side at j = 0
+    if (dim > 1)
+        for (int sx = 0; sx < epb; ++sx)
+            for (int py = 0; py <= epy; ++py)
+                for (int t = 0; t < NF1; ++t, e += 4) {
+                    const int ta = t % N1, tb = t / N1;
+                    const uint32_t nlo = (uint32_t)(ta + N1 * N1 * tb);           // j = 0
+                    const uint32_t nhi = (uint32_t)(ta + N1 * (N + N1 * tb));     // j = N
+                    FacePoint p;
+                    p.d = 1;
+                    p.need = (uint32_t)(sx + 1);
+                    p.needy = (uint32_t)(py == 0 ? 1 : py);
+                    if (py == 0) {    // own: row 0 (upper side), other: the row below the tile
+                        p.own_q = slot(sx, 0) * NP + nlo;
+                        p.own_lift = lift(1, slot(sx, 0), 0, t);
+                        p.oth_lower = 1;
+                        p.bsel = 2;
+                        p.goff = (uint32_t)sx * NP + nhi;
+                    } else {          // own: row py-1 (lower side), other: row py or outside
+                        p.own_q = slot(sx, py - 1) * NP + nhi;
+                        p.own_lift = lift(1, slot(sx, py - 1), 1, t);
+                        p.oth_lower = 0;
+                        p.bsel = 3;
+                        p.goff = (uint32_t)sx * NP + nlo;
+                        if (py < epy) {
+                            p.in_tile = 1;
+                            p.yplane = (uint32_t)py;
+                            p.oth_q = slot(sx, py) * NP + nlo;
+                            p.oth_lift = lift(1, slot(sx, py), 0, t);
+                        }
+                    }
+                    put(p, e);
+                }
+    // z-faces; face node t = i + N1 j
+    if (dim > 2)
+        for (int sy = 0; sy < epy; ++sy)
+            for (int sx = 0; sx < epb; ++sx)
+                for (int side = 0; side < 2; ++side)
+                    for (int t = 0; t < NF1; ++t, e += 4) {
+                        const uint32_t nlo = (uint32_t)t, nhi = (uint32_t)(t + N1 * N1 * N);
+                        FacePoint p;
+                        p.d = 2;
+                        p.need = (uint32_t)(sx + 1);
+                        p.needy = (uint32_t)(sy + 1);
+                        p.row = (uint32_t)sy;
+                        p.own_q = slot(sx, sy) * NP + (side == 0 ? nlo : nhi);
+                        p.own_lift = lift(2, slot(sx, sy), side, t);
+                        p.oth_lower = side == 0 ? 1 : 0;
+                        p.bsel = side == 0 ? 4 : 5;
+                        p.goff = (uint32_t)sx * NP + (side == 0 ? nhi : nlo);
+                        put(p, e);
+                    }
 }
 
 }  // namespace dg

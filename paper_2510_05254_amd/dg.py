@@ -46,6 +46,7 @@ SIGNATURES = {
     "dg_stream": (_P, [_P]),
     "dg_autotune": (_I, [_P, _I, _D, _I]),
     "dg_launch_config": (_I, [_P, _P, _I]),
+    "dg_set_launch_config": (_I, [_P, _P, _I]),
     "dg_last_error": (ctypes.c_char_p, []),
     "dg_batch_create": (_I, [_P, _I, _P]),
     "dg_batch_destroy": (_I, [_P]),
@@ -226,11 +227,23 @@ def dg_autotune(h, rk, dt, trial_steps=3):
     _call("dg_autotune", h, int(rk), float(dt), int(trial_steps))
 
 
+LAUNCH_CFG = 5
+
+
 def dg_launch_config(h):
-    """(tile order, z-slab, 1-D halo-bound divisor, tuned flag)."""
-    out = (ctypes.c_int64 * 4)()
-    _call("dg_launch_config", h, out, 4)
+    """(tile order, z-slab, 1-D halo-bound divisor, tuned flag, x-block)."""
+    out = (ctypes.c_int64 * LAUNCH_CFG)()
+    _call("dg_launch_config", h, out, LAUNCH_CFG)
     return tuple(int(x) for x in out)
+
+
+def dg_set_launch_config(h, cfg):
+    """Set (tile order, z-slab, 1-D halo-bound divisor, ignored, x-block)."""
+    vals = [int(x) for x in cfg]
+    if len(vals) != LAUNCH_CFG:
+        raise ValueError(f"a launch configuration has {LAUNCH_CFG} entries")
+    arr = (ctypes.c_int64 * LAUNCH_CFG)(*vals)
+    _call("dg_set_launch_config", h, arr, LAUNCH_CFG)
 
 
 def dg_stream(h) -> int:
@@ -307,6 +320,9 @@ class Solver:
 
     def launch_config(self):
         return dg_launch_config(self.h)
+
+    def set_launch_config(self, cfg):
+        dg_set_launch_config(self.h, cfg)
 
     def synchronize(self):
         dg_synchronize(self.h)

@@ -68,6 +68,8 @@ def main():
     ap.add_argument("--precision", required=True)
     ap.add_argument("--kernel", default="stage_kernel")
     ap.add_argument("--command", default="", help="the profiled command, recorded as is")
+    ap.add_argument("--launch-config", default=None,
+                    help="tile order, z-slab, x-block of the profiled run (bench.py's launch_config)")
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
     f = reduce(a.fetch, "FETCH_SIZE", a.kernel)
@@ -76,6 +78,8 @@ def main():
            "kernel_hash": kernel_hash(),
            "bytes_per_launch": f["bytes_per_launch"] + w["bytes_per_launch"],
            "fetch": f, "write": w, "command": a.command}
+    if a.launch_config:
+        rec["launch_config"] = [int(x) for x in a.launch_config.split(",")]
     with open(a.out, "w") as fh:
         json.dump(rec, fh, indent=1)
     print(json.dumps(rec))

@@ -51,6 +51,9 @@ def test_parity_rk3_rk6(dim, N, eq, rk):
     (1, 2, (7,), EUL), (2, 1, (10, 4), ADV),          # K_x < tile width: wrap inside a tile
     (3, 1, (3, 2, 16), EUL), (3, 4, (2, 2, 24), ADV),  # K_z split into XCD slabs
     (2, 7, (4, 9), EUL), (3, 5, (4, 1, 2), ADV),
+    # 3-D N = 4 tiles hold 2 x 2 elements: one row (its y-neighbours are
+    # itself), a ragged last row, one element, one layer
+    (3, 4, (3, 1, 2), EUL), (3, 4, (1, 5, 3), ADV), (3, 4, (1, 1, 1), EUL), (3, 4, (4, 3, 1), EUL),
 ])
 def test_parity_special_meshes(dim, N, K, eq):
     U0, Ug, Uo = _run_both(dim, N, K, eq, 4, 2)
@@ -247,10 +250,80 @@ def test_autotune_keeps_state_and_results(dim, N, K, eq, rk):
         ref = s.get_state()
         s.set_state(U0)
         cfg = s.autotune(rk, dt, 2)
-        assert cfg[3] == 1 and cfg[0] in (0, 1) and cfg[1] >= 1 and cfg[2] >= 3
+        assert cfg[3] == 1 and cfg[0] in (0, 1) and cfg[1] >= 1 and cfg[2] >= 3 and cfg[4] >= 1
         np.testing.assert_array_equal(s.get_state(), U0)
         s.step(rk, dt, 3)
         np.testing.assert_array_equal(s.get_state(), ref)
+
+
+# Every launch configuration (tile order, z-slab, x-block) visits the same
+# tiles in another order: the results are bitwise those of the default one,
+# also with a ragged last x-tile and x-blocks of one tile.
+@pytest.mark.parametrize("N,K,eq,cfgs", [
+    (4, (16, 5, 6), EUL, [(0, 1, 2), (0, 3, 4), (1, 6, 1), (0, 2, 8), (1, 1, 4)]),
+    (4, (15, 3, 4), ADV, [(0, 4, 2), (0, 1, 1), (1, 2, 4)]),
+    (1, (70, 3, 4), EUL, [(0, 2, 1), (1, 4, 3), (0, 1, 3)]),
+])
+def test_launch_configs_bitwise(N, K, eq, cfgs):
+    w, ax, U0, dt = case(3, N, K, eq, 22)
+    with dg.Solver(3, N, K, eq, params(3, eq)) as s:
+        base = s.launch_config()
+        assert base[3] == 0 and base[4] >= 1
+        refs = {}
+        for rk in (4, 3):
+            s.set_state(U0)
+            s.step(rk, dt, 2)
+            refs[rk] = s.get_state()
+        for order, slab, xblk in cfgs:
+            c = list(base)
+            c[0], c[1], c[4] = order, slab, xblk
+            s.set_launch_config(c)
+            got = s.launch_config()
+            assert (got[0], got[1], got[4], got[3]) == (order, slab, xblk, 0)
+            for rk in (4, 3):
+                s.set_state(U0)
+                s.step(rk, dt, 2)
+                np.testing.assert_array_equal(s.get_state(), refs[rk], err_msg=f"{(order, slab, xblk)} rk{rk}")
+
+
+def test_set_launch_config_errors():
+    w, ax, U0, dt = case(3, 4, (8, 3, 6), EUL, 5)
+    with dg.Solver(3, 4, (8, 3, 6), EUL, params(3, EUL)) as s:
+        base = list(s.launch_config())
+        assert base[4] == 4            # 8 elements, 2 per tile
+        for i, v in ((0, 2), (0, -1), (1, 4), (1, 0), (2, 0), (2, 2000), (4, 3), (4, 0)):
+            c = list(base)
+            c[i] = v
+            with pytest.raises(dg.DgError) as e:
+                s.set_launch_config(c)
+            assert e.value.status == dg.DG_EINVAL, (i, v)
+            assert s.launch_config() == tuple(base)
+        with pytest.raises(ValueError):
+            s.set_launch_config(base[:4])
+        with pytest.raises(dg.DgError) as e:
+            dg._call("dg_set_launch_config", s.h, (dg.ctypes.c_int64 * 5)(*base), 4)
+        assert e.value.status == dg.DG_EINVAL
+    with dg.Solver(2, 3, (5, 4), ADV, params(2, ADV)) as s:
+        base = list(s.launch_config())
+        for i, v in ((1, 2), (4, base[4] + 1)):
+            c = list(base)
+            c[i] = v
+            with pytest.raises(dg.DgError) as e:
+                s.set_launch_config(c)
+            assert e.value.status == dg.DG_EINVAL
+        c = list(base)
+        c[0] = 1
+        s.set_launch_config(c)
+        assert s.launch_config()[0] == 1
+        w2, ax2, U2, dt2 = case(2, 3, (5, 4), ADV, 6)
+        s.set_state(U2)
+        with dg.Batch() as b:
+            b.add(s, 4, dt2, 2)
+            with pytest.raises(dg.DgError) as e:
+                s.set_launch_config(base)
+            assert e.value.status == dg.DG_ESTATE
+            b.run_all()
+            b.synchronize()
 
 
 def test_autotune_error_paths():
