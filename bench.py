@@ -69,9 +69,10 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload: str, precision: str, launch_cfg):
-    """Measured HBM bytes per stage launch from profiles/, if the kernel and the
-    launch configuration (tile order, z-slab, x-block) are those measured."""
+def load_traffic(workload: str, precision: str, rk: int, launch_cfg):
+    """Measured HBM bytes per stage launch from profiles/, if the kernel, the RK
+    scheme and the launch configuration (tile order, z-slab, x-block) are
+    those measured."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{precision}.json")
     if not os.path.exists(path):
         return None
@@ -80,6 +81,8 @@ def load_traffic(workload: str, precision: str, launch_cfg):
     except (OSError, ValueError):
         return None
     if rec.get("kernel_hash") != kernel_hash():
+        return None
+    if rec.get("rk") != rk:
         return None
     cfg = rec.get("launch_config")
     if cfg is not None and list(cfg) != [launch_cfg[0], launch_cfg[1], launch_cfg[4]]:
@@ -294,7 +297,7 @@ def main():
     avg_launch_s = ms / 1e3 / launches
     alg_bytes = PASSES_PER_STEP[a.rk] / stages * w.unknowns * rsize
     achieved = alg_bytes / avg_launch_s / 1e9
-    traffic = load_traffic(w.name, a.precision, launch_cfg)
+    traffic = load_traffic(w.name, a.precision, a.rk, launch_cfg)
 
     # achievable bandwidth: a plain device-to-device copy of 2 GiB
     src = torch.empty(1 << 28, dtype=torch.float64, device="cuda")

@@ -540,12 +540,17 @@ int dg_create_ex(int dim, int N, const int64_t *K, int equation, const double *p
     h->tiles_x = (h->K[0] + h->epb - 1) / h->epb;
     h->epy = stage_epy(dim, N);
     h->tiles_y = (h->K[1] + h->epy - 1) / h->epy;
+    // default 3-D tile order: x-blocks of about an eighth of the x-tiles (the
+    // largest divisor in [4, max(4, tiles_x / 8)], else whole rows), walked
+    // y-tile by y-tile, then layer by layer: each XCD's contiguous range
+    // is then an x-column of the mesh, whose y- and z-neighbour traces stay
+    // in that XCD's L2 (z-slab 1)
     h->slab = 1;
-    if (dim == 3) {
-        for (int64_t s = std::max<int64_t>(1, h->K[2] / kXcds); s >= 1; --s)
-            if (h->K[2] % s == 0) { h->slab = s; break; }
-    }
     h->xblk = h->tiles_x;
+    if (dim == 3) {
+        for (int64_t xb = std::max<int64_t>(4, h->tiles_x / kXcds); xb >= 4; --xb)
+            if (h->tiles_x % xb == 0) { h->xblk = xb; break; }
+    }
     h->ntiles = h->tiles_x * h->tiles_y * h->K[2];
     h->grid = std::min<int64_t>(h->ntiles, kMaxGrid);
 

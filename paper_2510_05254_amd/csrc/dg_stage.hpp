@@ -40,9 +40,9 @@
 // Tile order: virtual block b runs on XCD b % 8 (private L2 per XCD); tiles
 // are renumbered so each XCD owns a contiguous range, in the order x-tile
 // fastest within an x-block of `xblk` tiles, then z inside a slab of `slab`
-// layers, then y, then slab, then x-block, which keeps the y- and
+// layers, then y-tile, then slab, then x-block, which keeps the y- and
 // z-neighbours of a tile among recently visited tiles (xblk slab and xblk
-// tiles back).
+// tiles back inside a slab).
 #pragma once
 
 #include <type_traits>
@@ -304,7 +304,7 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
     }
     const int64_t ex0 = tx * EPB, ey0 = ty * EPY;
     const int nact = (int)((K0 - ex0) < EPB ? (K0 - ex0) : EPB);      // active x slots
-    const int nacty = (int)((K1 - ey0) < EPY ? (K1 - ey0) : EPY);     // active rows
+    const int nacty = EPY == 1 ? 1 : (int)((K1 - ey0) < EPY ? (K1 - ey0) : EPY);     // active rows
     const int64_t ebase = K0 * (ey0 + K1 * ez);    // element index of (0, ey0, ez)
 
     // Neighbour element bases (node offsets) of this tile, uniform: bsel =
@@ -332,12 +332,18 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
     // bsel << 3 | other_in_tile << 6 | row << 7 | need << 8 | xplane << 16 |
     // needy << 24 | yplane << 28, w1 = own_q | other_q << 16, w2 = outside
     // node offset, w3 = lift slots.
+    // (one-row tiles: every point has needy = 1 and no in-tile y-plane)
     auto face_valid = [nact, nacty](uint32_t w0) {
-        return ((w0 >> 8) & 0xffu) <= uint32_t(nact) && ((w0 >> 24) & 0xfu) <= uint32_t(nacty);
+        const bool x = ((w0 >> 8) & 0xffu) <= uint32_t(nact);
+        (void)nacty;
+        if constexpr (EPY == 1) return x;
+        else return x && ((w0 >> 24) & 0xfu) <= uint32_t(nacty);
     };
     auto other_outside = [nact, nacty](uint32_t w0) {
-        return ((w0 >> 6) & 1u) == 0 || ((w0 >> 16) & 0xffu) == uint32_t(nact) ||
-               (w0 >> 28) == uint32_t(nacty);
+        const bool o = ((w0 >> 6) & 1u) == 0 || ((w0 >> 16) & 0xffu) == uint32_t(nact);
+        (void)nacty;
+        if constexpr (EPY == 1) return o;
+        else return o || (w0 >> 28) == uint32_t(nacty);
     };
     // blend of the six bases by masks (bitwise, so it stays in registers)
     auto outside_node = [nb0, nb1, nb2, nb3, nb4, nb5, rstride](uint32_t w0, uint32_t w2) -> idx_t {
@@ -354,9 +360,10 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
 
     // ---- phase 1: state, 1/rho and flux tensor into LDS; the outside trace
     // of this thread's first face point is prefetched behind the own state.
-    const bool active = ts.sx < nact && ts.sy < nacty;
+    const bool active = EPY == 1 ? slot < nact : ts.sx < nact && ts.sy < nacty;
     const int ln = slot * NP + n;
-    const idx_t gi = idx_t((ebase + K0 * ts.sy + ex0 + ts.sx) * NP + n);
+    const idx_t gi = EPY == 1 ? idx_t((ebase + ex0 + slot) * NP + n)
+                              : idx_t((ebase + K0 * ts.sy + ex0 + ts.sx) * NP + n);
     // both groups are loaded unconditionally (inactive lanes read node 0) so
     // the wait before the LDS stores covers only the first group
     // Issue order matters (vector loads retire in order): this thread's first

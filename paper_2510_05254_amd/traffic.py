@@ -68,6 +68,7 @@ def main():
     ap.add_argument("--precision", required=True)
     ap.add_argument("--kernel", default="stage_kernel")
     ap.add_argument("--command", default="", help="the profiled command, recorded as is")
+    ap.add_argument("--rk", type=int, default=4, help="RK scheme of the profiled run")
     ap.add_argument("--launch-config", default=None,
                     help="tile order, z-slab, x-block of the profiled run (bench.py's launch_config)")
     ap.add_argument("--out", required=True)
@@ -75,7 +76,7 @@ def main():
     f = reduce(a.fetch, "FETCH_SIZE", a.kernel)
     w = reduce(a.write, "WRITE_SIZE", a.kernel)
     rec = {"workload": a.workload, "precision": a.precision, "kernel": a.kernel,
-           "kernel_hash": kernel_hash(),
+           "kernel_hash": kernel_hash(), "rk": a.rk,
            "bytes_per_launch": f["bytes_per_launch"] + w["bytes_per_launch"],
            "fetch": f, "write": w, "command": a.command}
     if a.launch_config:
