@@ -174,26 +174,24 @@ struct Arr<real, true> {
         r = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0,
                                               (int)(uint32_t(nvar) * vbytes), 0x00020000);
     }
-    // POL: cache-policy bits of the buffer instruction (2 = non-temporal on gfx950)
-    template <int POL = 0>
+    // (last argument: the instruction's cache-policy bits, default policy)
     __device__ __forceinline__ real ld(int v, idx_t node) const
     {
         if constexpr (sizeof(real) == 8)
             return __builtin_bit_cast(real, __builtin_amdgcn_raw_buffer_load_b64(
-                                                r, node * (uint32_t)sizeof(real), v * vbytes, POL));
+                                                r, node * (uint32_t)sizeof(real), v * vbytes, 0));
         else
             return __builtin_bit_cast(real, __builtin_amdgcn_raw_buffer_load_b32(
-                                                r, node * (uint32_t)sizeof(real), v * vbytes, POL));
+                                                r, node * (uint32_t)sizeof(real), v * vbytes, 0));
     }
-    template <int POL = 0>
     __device__ __forceinline__ void st(int v, idx_t node, real x) const
     {
         if constexpr (sizeof(real) == 8)
             __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r,
-                                                  node * (uint32_t)sizeof(real), v * vbytes, POL);
+                                                  node * (uint32_t)sizeof(real), v * vbytes, 0);
         else
             __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), r,
-                                                  node * (uint32_t)sizeof(real), v * vbytes, POL);
+                                                  node * (uint32_t)sizeof(real), v * vbytes, 0);
     }
 };
 
@@ -204,18 +202,8 @@ struct Arr<real, false> {
     int64_t stride;
     __device__ __forceinline__ Arr(const void *ptr, int64_t s, int)
         : p(static_cast<real *>(const_cast<void *>(ptr))), stride(s) {}
-    template <int POL = 0>
-    __device__ __forceinline__ real ld(int v, idx_t node) const
-    {
-        if constexpr (POL != 0) return __builtin_nontemporal_load(p + v * stride + node);
-        else return p[v * stride + node];
-    }
-    template <int POL = 0>
-    __device__ __forceinline__ void st(int v, idx_t node, real x) const
-    {
-        if constexpr (POL != 0) __builtin_nontemporal_store(x, p + v * stride + node);
-        else p[v * stride + node] = x;
-    }
+    __device__ __forceinline__ real ld(int v, idx_t node) const { return p[v * stride + node]; }
+    __device__ __forceinline__ void st(int v, idx_t node, real x) const { p[v * stride + node] = x; }
 };
 
 // LDS of one stage-kernel workgroup
@@ -253,8 +241,7 @@ struct ThreadSetup {
 // number of RK inputs (p.nin) at compile time, so their loads are issued in
 // phase 1 behind the outside traces with exact waits; NIN = -1 reads p.nin and
 // loads the inputs in phase 3.
-template <typename real, int DIM, int N, int EQ, bool BUF, int SPOL, int YPOL, int TM, bool XIN = false,
-          int NIN = -1>
+template <typename real, int DIM, int N, int EQ, bool BUF, int TM, bool XIN = false, int NIN = -1>
 __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
                                            StageLds<real, DIM, N, EQ, TM> &lds,
                                            const ThreadSetup<DIM, N, TM> &ts, real dval,
@@ -390,7 +377,7 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
     real y[NV], g[NV];
     const idx_t gy = active ? gi : idx_t(0);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) y[v] = yin.template ld<YPOL>(v, gy);
+    for (int v = 0; v < NV; ++v) y[v] = yin.ld(v, gy);
     const bool pre = tid < NF && face_valid(fw0) && other_outside(fw0);
     const idx_t gn0 = pre ? outside_node(fw0, fw2) : idx_t(0);
 #pragma unroll
@@ -408,12 +395,12 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
     if constexpr (NIN >= 1) {
         const A in0(p.in0, p.stride, NV);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) a0[v] = in0.template ld<SPOL>(v, gy);
+        for (int v = 0; v < NV; ++v) a0[v] = in0.ld(v, gy);
     }
     if constexpr (NIN >= 2) {
         const A in1(p.in1, p.stride, NV);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) a1[v] = in1.template ld<SPOL>(v, gy);
+        for (int v = 0; v < NV; ++v) a1[v] = in1.ld(v, gy);
     }
     const bool has0 = NIN < 0 ? p.nin > 0 : NIN >= 1;
     const bool has1 = NIN < 0 ? p.nin > 1 : NIN >= 2;
@@ -550,12 +537,12 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
         if (NIN < 0 && p.nin > 0) {
             const A in0(p.in0, p.stride, NV);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) a0[v] = in0.template ld<SPOL>(v, gi);
+            for (int v = 0; v < NV; ++v) a0[v] = in0.ld(v, gi);
         }
         if (NIN < 0 && p.nin > 1) {
             const A in1(p.in1, p.stride, NV);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) a1[v] = in1.template ld<SPOL>(v, gi);
+            for (int v = 0; v < NV; ++v) a1[v] = in1.ld(v, gi);
         }
 #pragma unroll
         for (int o = 0; o < 2; ++o) {
@@ -573,7 +560,7 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
                         real val = cy * y[v];
                         if (has0) val = fmadd(c0, a0[v], val);
                         if (has1) val = fmadd(c1, a1[v], val);
-                        out.template st<SPOL>(v, gi, fmadd(cr, R[v], val));
+                        out.st(v, gi, fmadd(cr, R[v], val));
                     }
                 } else {
                     // fused RK6 stages: also the stored k's with nonzero weights
@@ -589,17 +576,17 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
                         const real cj = real(x->c[o][j]);
                         const A in(x->in[j], p.stride, NV);
 #pragma unroll
-                        for (int v = 0; v < NV; ++v) val[v] = fmadd(cj, in.template ld<SPOL>(v, gi), val[v]);
+                        for (int v = 0; v < NV; ++v) val[v] = fmadd(cj, in.ld(v, gi), val[v]);
                     }
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) out.template st<SPOL>(v, gi, fmadd(cr, R[v], val[v]));
+                    for (int v = 0; v < NV; ++v) out.st(v, gi, fmadd(cr, R[v], val[v]));
                 }
             }
         }
     }
 }
 
-template <typename real, int DIM, int N, int EQ, bool BUF, int NIN, int SPOL = 0, int YPOL = 0, int TM = 1>
+template <typename real, int DIM, int N, int EQ, bool BUF, int NIN, int TM = 1>
 __global__ void __launch_bounds__((Geo<DIM, N, TM>::THREADS)) __attribute__((amdgpu_waves_per_eu(4)))
 stage_kernel(const StageParams p)
 {
@@ -611,7 +598,7 @@ stage_kernel(const StageParams p)
         // tile number: XCD-contiguous renumbering of the virtual block
         const uint32_t xb = vb & (kXcds - 1), jb = vb / kXcds;
         const uint32_t L = p.plain_order ? vb : xb * p.xq + (xb < p.xr ? xb : p.xr) + jb;
-        stage_tile<real, DIM, N, EQ, BUF, SPOL, YPOL, TM, false, NIN>(p, L, lds, ts, dval);
+        stage_tile<real, DIM, N, EQ, BUF, TM, false, NIN>(p, L, lds, ts, dval);
         __syncthreads();
     }
 }
@@ -628,7 +615,7 @@ stage_kernel_x(const StageParams p, const ExtraIn x)
     for (uint32_t vb = blockIdx.x; vb < p.ntiles32; vb += gridDim.x) {
         const uint32_t xb = vb & (kXcds - 1), jb = vb / kXcds;
         const uint32_t L = p.plain_order ? vb : xb * p.xq + (xb < p.xr ? xb : p.xr) + jb;
-        stage_tile<real, DIM, N, EQ, BUF, 0, 0, 1, true>(p, L, lds, ts, dval, &x);
+        stage_tile<real, DIM, N, EQ, BUF, 1, true>(p, L, lds, ts, dval, &x);
         __syncthreads();
     }
 }
@@ -649,7 +636,7 @@ stage_kernel_batch(const BatchLaunch b)
         const uint32_t xb = vb & (kXcds - 1), jb = vb / kXcds;
         const uint32_t T = xb * b.xq + (xb < b.xr ? xb : b.xr) + jb;
         const uint32_t s = b.tile_solve[T];
-        stage_tile<real, DIM, N, EQ, BUF, 0, 0, 1, false, NIN>(b.params[s], T - b.tile_base[s], lds, ts, dval);
+        stage_tile<real, DIM, N, EQ, BUF, 1, false, NIN>(b.params[s], T - b.tile_base[s], lds, ts, dval);
         __syncthreads();
     }
 }
