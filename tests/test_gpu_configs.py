@@ -8,6 +8,9 @@ configuration bench.py times.
   2-D Euler 5, 3-D Euler 1 step); then the full step count on the GPU alone,
   checked by properties that hold at any size: mass conservation and, for
   advection, the exact translated solution.
+* A mesh whose state arrays exceed 2 GiB (the stage kernels' 64-bit
+  addressing path, which none of the configurations reaches): every output
+  against the oracle after one RK4 and one RK6 step.
 """
 import functools
 import sys
@@ -111,3 +114,24 @@ def test_config_fp32_against_fp64_oracle(cid, steps, bar):
         err = rel_l2_per_var(Ug, Uo)
     _say(f"config {cid} FP32, {steps} RK4 steps: rel L2 per var vs FP64 oracle {err}")
     assert np.all(err <= bar), err
+
+
+# 3-D Euler N = 4 on 84 x 81 x 80 elements: 2.18 GB per state array, so the
+# stage kernels address it with 64-bit pointers; tiles of 2 x 2 elements with
+# a ragged last row.
+@pytest.mark.parametrize("rk", [4, 6])
+def test_64bit_addressing_parity(rk):
+    from _helpers import EUL, case, params
+    K = (84, 81, 80)
+    w, ax, U0, dt = case(3, 4, K, EUL, 31)
+    assert U0.nbytes >= 2 ** 31
+    _say(f"64-bit path: K={K}, {U0.nbytes / 1e9:.2f} GB per array, rk={rk}")
+    with dg.Solver(3, 4, K, EUL, params(3, EUL)) as s:
+        s.set_state(U0)
+        s.step(rk, dt, 1)
+        Ug = s.get_state()
+    Uo = oracle.step(3, 4, K, EUL, params(3, EUL), U0, rk, dt, 1)
+    err = rel_l2_per_var(Ug, Uo)
+    _say(f"rel L2 per var {err}")
+    assert np.all(err <= PARITY_RTOL), err
+    assert rel_l2_per_var(Uo, U0).max() > 1e3 * PARITY_RTOL
