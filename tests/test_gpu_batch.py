@@ -69,6 +69,45 @@ def test_batch_matches_single_solves(graph):
         s.close()
 
 
+# FP32 members (1-D chunked and whole, 2-D, 3-D with 2 x 2 tiles and a ragged
+# last row; RK3 and RK4): bitwise the FP32 dg_step result, and within the
+# FP32 bar of the FP64 oracle.
+MIX32 = [  # (dim, N, K, eq, rk, nsteps)
+    (1, 5, (3000,), EUL, 4, 9),
+    (1, 3, (50,), ADV, 3, 6),
+    (2, 3, (9, 5), EUL, 4, 5),
+    (2, 7, (6, 4), ADV, 4, 5),
+    (3, 4, (3, 3, 2), EUL, 4, 5),
+    (3, 2, (5, 3, 2), ADV, 3, 4),
+]
+FP32_BAR = 2e-5      # relative L2 per variable after <= 9 steps (u = 6e-8 per stage operation)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_fp32_matches_single_solves(graph):
+    made = []
+    with dg.Batch(graph=graph) as b:
+        for i, (dim, N, K, eq, rk, n) in enumerate(MIX32):
+            w, ax, U0, dt = case(dim, N, K, eq, 300 + i)
+            s = dg.Solver(dim, N, K, eq, params(dim, eq), precision=dg.DG_FP32)
+            s.set_state(U0)
+            b.add(s, rk, dt, n)
+            made.append((s, U0, dt))
+        b.run_all()
+        for (dim, N, K, eq, rk, n), (s, U0, dt) in zip(MIX32, made):
+            Ub = s.get_state()
+            with dg.Solver(dim, N, K, eq, params(dim, eq), precision=dg.DG_FP32) as a:
+                a.set_state(U0)
+                a.step(rk, dt, n)
+                np.testing.assert_array_equal(Ub, a.get_state())
+            Uo = oracle.step(dim, N, K, eq, params(dim, eq), U0, rk, dt, n)
+            err = rel_l2_per_var(Ub, Uo)
+            print(f"fp32 batch member dim={dim} N={N} K={K} rk={rk}: rel L2 {err}")
+            assert np.all(err <= FP32_BAR), err
+    for s, _, _ in made:
+        s.close()
+
+
 def test_continuous_admission_and_graph_replays():
     """Members join while others run; graph ticks replayed with host work between."""
     specs = [(2, 3, (6, 5), EUL, 4, 12), (1, 4, (20,), ADV, 4, 7), (2, 3, (4, 4), EUL, 4, 9)]

@@ -236,6 +236,25 @@ def test_fp32_against_fp64_oracle(dim, N, eq):
     np.testing.assert_allclose(m, oracle.mass(dim, N, K, eq, Uo), rtol=1e-6, atol=1e-7)
 
 
+# FP32 on the other paths: 1-D chunked meshes (temporally blocked kernel,
+# several launches), RK3 and RK6, 3-D N = 4 tiles of 2 x 2 elements.
+@pytest.mark.parametrize("dim,N,K,eq,rk,nsteps,bar", [
+    (1, 5, (3000,), EUL, 4, 20, 1e-5), (1, 2, (700,), ADV, 3, 30, 1e-5),
+    (2, 4, (9, 7), EUL, 6, 3, 1e-5), (3, 4, (5, 3, 2), EUL, 3, 3, 1e-5), (3, 4, (3, 2, 3), ADV, 6, 2, 1e-5),
+])
+def test_fp32_other_paths(dim, N, K, eq, rk, nsteps, bar):
+    w, ax, U0, dt = case(dim, N, K, eq, 44)
+    with dg.Solver(dim, N, K, eq, params(dim, eq), precision=dg.DG_FP32) as s:
+        s.set_state(U0)
+        s.step(rk, dt, nsteps)
+        Ug = s.get_state()
+    Uo = oracle.step(dim, N, K, eq, params(dim, eq), U0, rk, dt, nsteps)
+    err = rel_l2_per_var(Ug, Uo)
+    print(f"fp32 dim={dim} N={N} K={K} rk={rk} steps={nsteps}: rel L2 per var {err}")
+    assert np.all(err <= bar), err
+    assert rel_l2_per_var(Uo, U0).max() > 10 * bar     # the state really moved
+
+
 # The autotuner times launch configurations that all compute the same bits:
 # afterwards the state is the one set, and stepping gives bitwise what the
 # default configuration gives.
