@@ -54,6 +54,8 @@ def test_library_exports_every_declared_symbol():
     ((1, 3, [4], 1, [-1.0]), "sound speed"),
     ((2, 3, [4, 4], 0, [1.0, float("nan")]), "velocity"),
     ((1, 3, [4], 1, [float("inf")]), "sound speed"),
+    ((1, 3, [2 ** 30 + 1], 0, [1.0]), "K"),                        # maximum size per direction
+    ((3, 1, [2 ** 11, 2 ** 11, 2 ** 10], 1, [1.0]), "elements"),   # more than 4e9 elements
 ])
 def test_create_rejects_invalid_arguments(args, why):
     with pytest.raises(dg.DgError) as e:
@@ -93,6 +95,11 @@ def test_workspace_bytes():
     assert 4 * arr // 2 <= b4f < b4
     with pytest.raises(dg.DgError):
         dg.dg_workspace_bytes(3, 4, [64, 64, 64], 1, dg.DG_FP64, 5)
+    # the largest meshes the validation admits are sized without overflow
+    big = dg.dg_workspace_bytes(1, 8, [2 ** 30], 1, dg.DG_FP64, 4)
+    assert big >= 4 * 2 ** 30 * 9 * 2 * 8
+    big3 = dg.dg_workspace_bytes(3, 8, [2 ** 11, 2 ** 11, 953], 1, dg.DG_FP64, 6)
+    assert big3 >= 9 * (2 ** 22 * 953) * 729 * 4 * 8
 
 
 @pytest.mark.skipif(_has_gpu(), reason="checks the no-device path")
