@@ -20,8 +20,9 @@
 // threads), times two rows along y for 3-D N = 4 (512 threads), and runs
 // three phases separated by barriers:
 //  1. node-parallel: load the stage input (one thread per node, variables in
-//     registers), stage it in LDS together with 1/rho and the symmetric
-//     momentum-flux tensor m_a m_b / rho + delta_ab rho c^2;
+//     registers), stage it in LDS together with, for Euler, either 1/rho and
+//     the symmetric momentum-flux tensor m_a m_b / rho + delta_ab rho c^2 or
+//     the velocities m_k / rho (StageLds);
 //  2. face-parallel: one thread per face point of the tile (a host-built
 //     descriptor table lists them). Faces inside the tile read both sides from
 //     LDS and are evaluated once; faces to neighbouring tiles read the other
@@ -52,6 +53,16 @@
 namespace dg {
 
 constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+
+// Waves per SIMD the register allocation of the single-solve stage kernel
+// targets: six where the velocity LDS layout lets three 512-thread
+// workgroups share a CU (3-D N = 4 FP64: 47 KB each instead of 63 KB) and the
+// registers fit without spilling (32-bit addressing), four elsewhere. The
+// six-wave kernels use that layout and load the RK inputs in phase 3.
+constexpr int stage_waves(int DIM, int N, int rbytes, bool BUF)
+{
+    return DIM == 3 && N == 4 && rbytes == 8 && BUF ? 6 : 4;
+}
 
 // Rows of elements along y per tile: two for 3-D N = 4, whose tile of 2 x 2
 // elements (512 threads) reads half the y-face traces per element of a 2 x 1
@@ -114,6 +125,17 @@ __device__ __forceinline__ real sym_flux(real ma, real mb, real rho, real rinv, 
 {
 #pragma clang fp contract(off)
     real f = ma * (mb * rinv);
+    if (diag) f = f + rho * c2;
+    return f;
+}
+
+// The same entry from m_a and the velocity v_b = m_b (1/rho) that phase 1
+// stores: the operations of sym_flux in its order, so the same bits.
+template <typename real>
+__device__ __forceinline__ real sym_flux_v(real ma, real vb, real rho, real c2, bool diag)
+{
+#pragma clang fp contract(off)
+    real f = ma * vb;
     if (diag) f = f + rho * c2;
     return f;
 }
@@ -206,14 +228,18 @@ struct Arr<real, false> {
     __device__ __forceinline__ void st(int v, idx_t node, real x) const { p[v * stride + node] = x; }
 };
 
-// LDS of one stage-kernel workgroup
-template <typename real, int DIM, int N, int EQ, int TM>
+// LDS of one stage-kernel workgroup. Per node, Euler keeps either the
+// symmetric momentum-flux tensor and 1/rho (VEL = false: fewest LDS reads and
+// flops in the volume term) or the velocities m_k (1/rho) (VEL = true:
+// smaller, so that more workgroups share a CU; the tensor entries are rebuilt
+// from them with the same operations, so the results are the same bits).
+template <typename real, int DIM, int N, int EQ, int TM, bool VEL>
 struct StageLds {
     using G = Geo<DIM, N, TM>;
     static constexpr int NV = Vars<EQ, DIM>::NV, NSYM = Vars<EQ, DIM>::NSYM;
+    static constexpr int NE = EQ == 0 ? 1 : (VEL ? DIM : NSYM + 1);
     real sY[NV][G::TN];
-    real sP[NSYM > 0 ? NSYM : 1][EQ == 1 ? G::TN : 1];
-    real sRi[EQ == 1 ? G::TN : 1];
+    real sE[NE][EQ == 1 ? G::TN : 1];   // VEL: v_k; otherwise tensor (sym_index order), then 1/rho
     real sL[NV][G::NL];
     real sD[G::N1 * G::N1];
 };
@@ -241,9 +267,10 @@ struct ThreadSetup {
 // number of RK inputs (p.nin) at compile time, so their loads are issued in
 // phase 1 behind the outside traces with exact waits; NIN = -1 reads p.nin and
 // loads the inputs in phase 3.
-template <typename real, int DIM, int N, int EQ, bool BUF, int TM, bool XIN = false, int NIN = -1>
+template <typename real, int DIM, int N, int EQ, bool BUF, int TM, bool XIN = false, int NIN = -1,
+          int WAVES = 4, bool VEL = false>
 __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
-                                           StageLds<real, DIM, N, EQ, TM> &lds,
+                                           StageLds<real, DIM, N, EQ, TM, VEL> &lds,
                                            const ThreadSetup<DIM, N, TM> &ts, real dval,
                                            const ExtraIn *x = nullptr)
 {
@@ -255,8 +282,8 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
     using A = Arr<real, BUF>;
     using idx_t = typename A::idx_t;
     auto &sY = lds.sY;
-    auto &sP = lds.sP;
-    auto &sRi = lds.sRi;
+    auto &sE = lds.sE;
+    constexpr int NSYM = Vars<EQ, DIM>::NSYM;
     auto &sL = lds.sL;
     auto &sD = lds.sD;
     const int tid = ts.tid, slot = ts.slot, n = ts.n;
@@ -390,14 +417,16 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
         for (int v = 0; v < NV; ++v) g2[v] = yin.ld(v, gn2);
     }
     // RK inputs, issued last: the waits for the own state and the traces do
-    // not cover them
+    // not cover them. Kernels built for six waves per SIMD load them in
+    // phase 3 instead, so they are not held in registers across the phases.
+    constexpr bool EARLY = NIN >= 0 && WAVES == 4;
     real a0[NV], a1[NV];
-    if constexpr (NIN >= 1) {
+    if constexpr (EARLY && NIN >= 1) {
         const A in0(p.in0, p.stride, NV);
 #pragma unroll
         for (int v = 0; v < NV; ++v) a0[v] = in0.ld(v, gy);
     }
-    if constexpr (NIN >= 2) {
+    if constexpr (EARLY && NIN >= 2) {
         const A in1(p.in1, p.stride, NV);
 #pragma unroll
         for (int v = 0; v < NV; ++v) a1[v] = in1.ld(v, gy);
@@ -412,12 +441,19 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
         for (int v = 0; v < NV; ++v) sY[v][ln] = y[v];
         if constexpr (EQ == 1) {
             const real rinv = recip(y[0]);
-            sRi[ln] = rinv;
+            if constexpr (VEL) {
+                // m_b (1/rho) as sym_flux and wave_speed form it; the tensor
+                // entries are rebuilt from these where they are needed
 #pragma unroll
-            for (int a = 0; a < DIM; ++a)
+                for (int k = 0; k < DIM; ++k) sE[k][ln] = y[1 + k] * rinv;
+            } else {
+                sE[NSYM][ln] = rinv;
 #pragma unroll
-                for (int b = a; b < DIM; ++b)
-                    sP[sym_index(a, b, DIM)][ln] = sym_flux(y[1 + a], y[1 + b], y[0], rinv, c2, a == b);
+                for (int a = 0; a < DIM; ++a)
+#pragma unroll
+                    for (int b = a; b < DIM; ++b)
+                        sE[sym_index(a, b, DIM)][ln] = sym_flux(y[1 + a], y[1 + b], y[0], rinv, c2, a == b);
+            }
         }
     }
     __syncthreads();
@@ -463,9 +499,19 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
                     lam = fabs(par[D]);
                 } else {
                     F[0] = U[1 + D];
+                    if constexpr (VEL) {
 #pragma unroll
-                    for (int k = 0; k < DIM; ++k) F[1 + k] = sP[sym_index(D, k, DIM)][q];
-                    lam = wave_speed(F[0], sRi[q], par[0]);
+                        for (int k = 0; k < DIM; ++k) {
+                            const int a = D < k ? D : k, b = D < k ? k : D;
+                            F[1 + k] = sym_flux_v(U[1 + a], sE[b][q], U[0], c2, a == b);
+                        }
+                        // |m_D (1/rho)| + c, as wave_speed forms it
+                        lam = fabs(sE[D][q]) + par[0];
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < DIM; ++k) F[1 + k] = sE[sym_index(D, k, DIM)][q];
+                        lam = wave_speed(F[0], sE[NSYM][q], par[0]);
+                    }
                 }
             };
             from_lds(own_q, Uo, Fo, lo);
@@ -517,7 +563,14 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
                 } else {
                     acc[0] += dm * sY[1 + d][q];
 #pragma unroll
-                    for (int k = 0; k < DIM; ++k) acc[1 + k] += dm * sP[sym_index(d, k, DIM)][q];
+                    for (int k = 0; k < DIM; ++k) {
+                        if constexpr (VEL) {
+                            const int a = d < k ? d : k, b = d < k ? k : d;
+                            acc[1 + k] += dm * sym_flux_v(sY[1 + a][q], sE[b][q], sY[0][q], c2, a == b);
+                        } else {
+                            acc[1 + k] += dm * sE[sym_index(d, k, DIM)][q];
+                        }
+                    }
                 }
             }
             if constexpr (EQ == 0) {
@@ -534,12 +587,12 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
                 for (int v = 0; v < NV; ++v) R[v] += sL[v][li];
             }
         }
-        if (NIN < 0 && p.nin > 0) {
+        if (!EARLY && has0) {
             const A in0(p.in0, p.stride, NV);
 #pragma unroll
             for (int v = 0; v < NV; ++v) a0[v] = in0.ld(v, gi);
         }
-        if (NIN < 0 && p.nin > 1) {
+        if (!EARLY && has1) {
             const A in1(p.in1, p.stride, NV);
 #pragma unroll
             for (int v = 0; v < NV; ++v) a1[v] = in1.ld(v, gi);
@@ -587,18 +640,20 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
 }
 
 template <typename real, int DIM, int N, int EQ, bool BUF, int NIN, int TM = 1>
-__global__ void __launch_bounds__((Geo<DIM, N, TM>::THREADS)) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__((Geo<DIM, N, TM>::THREADS))
+__attribute__((amdgpu_waves_per_eu(stage_waves(DIM, N, (int)sizeof(real), BUF))))
 stage_kernel(const StageParams p)
 {
     using G = Geo<DIM, N, TM>;
-    __shared__ StageLds<real, DIM, N, EQ, TM> lds;
+    constexpr int W = stage_waves(DIM, N, (int)sizeof(real), BUF);
+    __shared__ StageLds<real, DIM, N, EQ, TM, W == 6> lds;
     const ThreadSetup<DIM, N, TM> ts;
     const real dval = ts.tid < G::N1 * G::N1 ? static_cast<const real *>(p.D)[ts.tid] : real(0);
     for (uint32_t vb = blockIdx.x; vb < p.ntiles32; vb += gridDim.x) {
         // tile number: XCD-contiguous renumbering of the virtual block
         const uint32_t xb = vb & (kXcds - 1), jb = vb / kXcds;
         const uint32_t L = p.plain_order ? vb : xb * p.xq + (xb < p.xr ? xb : p.xr) + jb;
-        stage_tile<real, DIM, N, EQ, BUF, TM, false, NIN>(p, L, lds, ts, dval);
+        stage_tile<real, DIM, N, EQ, BUF, TM, false, NIN, W, W == 6>(p, L, lds, ts, dval);
         __syncthreads();
     }
 }
@@ -609,7 +664,7 @@ __global__ void __launch_bounds__((Geo<DIM, N>::THREADS)) __attribute__((amdgpu_
 stage_kernel_x(const StageParams p, const ExtraIn x)
 {
     using G = Geo<DIM, N>;
-    __shared__ StageLds<real, DIM, N, EQ, 1> lds;
+    __shared__ StageLds<real, DIM, N, EQ, 1, false> lds;
     const ThreadSetup<DIM, N, 1> ts;
     const real dval = ts.tid < G::N1 * G::N1 ? static_cast<const real *>(p.D)[ts.tid] : real(0);
     for (uint32_t vb = blockIdx.x; vb < p.ntiles32; vb += gridDim.x) {
@@ -629,7 +684,7 @@ __global__ void __launch_bounds__((Geo<DIM, N>::THREADS)) __attribute__((amdgpu_
 stage_kernel_batch(const BatchLaunch b)
 {
     using G = Geo<DIM, N>;
-    __shared__ StageLds<real, DIM, N, EQ, 1> lds;
+    __shared__ StageLds<real, DIM, N, EQ, 1, false> lds;
     const ThreadSetup<DIM, N, 1> ts;
     const real dval = ts.tid < G::N1 * G::N1 ? static_cast<const real *>(b.D)[ts.tid] : real(0);
     for (uint32_t vb = blockIdx.x; vb < b.ntiles; vb += gridDim.x) {
