@@ -54,14 +54,24 @@ namespace dg {
 
 constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 
-// Waves per SIMD the register allocation of the single-solve stage kernel
-// targets: six where the velocity LDS layout lets three 512-thread
-// workgroups share a CU (3-D N = 4 FP64: 47 KB each instead of 63 KB) and the
-// registers fit without spilling (32-bit addressing), four elsewhere. The
-// six-wave kernels use that layout and load the RK inputs in phase 3.
-constexpr int stage_waves(int DIM, int N, int rbytes, bool BUF)
+// LDS layout and register target of the single-solve stage kernel, by class
+// (3-D isothermal Euler, FP64, 32-bit addressing; all others keep the tensor
+// layout and four waves per SIMD). The velocity layout shrinks the
+// workgroup's LDS so that more workgroups share a CU: N = 1 by itself
+// (4 instead of 3 workgroups of 256 threads), N = 4, 7, 8 together with a
+// six-waves-per-SIMD register target (3 instead of 2, 3 instead of 2, 2
+// instead of 1). Six-wave kernels load the RK inputs in phase 3.
+constexpr bool stage_big_euler(int DIM, int EQ, int rbytes, bool BUF)
 {
-    return DIM == 3 && N == 4 && rbytes == 8 && BUF ? 6 : 4;
+    return DIM == 3 && EQ == 1 && rbytes == 8 && BUF;
+}
+constexpr int stage_waves(int DIM, int N, int EQ, int rbytes, bool BUF)
+{
+    return stage_big_euler(DIM, EQ, rbytes, BUF) && (N == 4 || N == 7 || N == 8) ? 6 : 4;
+}
+constexpr bool stage_vel(int DIM, int N, int EQ, int rbytes, bool BUF)
+{
+    return stage_big_euler(DIM, EQ, rbytes, BUF) && (N == 1 || N == 4 || N == 7 || N == 8);
 }
 
 // Rows of elements along y per tile: two for 3-D N = 4, whose tile of 2 x 2
@@ -641,19 +651,20 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
 
 template <typename real, int DIM, int N, int EQ, bool BUF, int NIN, int TM = 1>
 __global__ void __launch_bounds__((Geo<DIM, N, TM>::THREADS))
-__attribute__((amdgpu_waves_per_eu(stage_waves(DIM, N, (int)sizeof(real), BUF))))
+__attribute__((amdgpu_waves_per_eu(stage_waves(DIM, N, EQ, (int)sizeof(real), BUF))))
 stage_kernel(const StageParams p)
 {
     using G = Geo<DIM, N, TM>;
-    constexpr int W = stage_waves(DIM, N, (int)sizeof(real), BUF);
-    __shared__ StageLds<real, DIM, N, EQ, TM, W == 6> lds;
+    constexpr int W = stage_waves(DIM, N, EQ, (int)sizeof(real), BUF);
+    constexpr bool VEL = stage_vel(DIM, N, EQ, (int)sizeof(real), BUF);
+    __shared__ StageLds<real, DIM, N, EQ, TM, VEL> lds;
     const ThreadSetup<DIM, N, TM> ts;
     const real dval = ts.tid < G::N1 * G::N1 ? static_cast<const real *>(p.D)[ts.tid] : real(0);
     for (uint32_t vb = blockIdx.x; vb < p.ntiles32; vb += gridDim.x) {
         // tile number: XCD-contiguous renumbering of the virtual block
         const uint32_t xb = vb & (kXcds - 1), jb = vb / kXcds;
         const uint32_t L = p.plain_order ? vb : xb * p.xq + (xb < p.xr ? xb : p.xr) + jb;
-        stage_tile<real, DIM, N, EQ, BUF, TM, false, NIN, W, W == 6>(p, L, lds, ts, dval);
+        stage_tile<real, DIM, N, EQ, BUF, TM, false, NIN, W, VEL>(p, L, lds, ts, dval);
         __syncthreads();
     }
 }
