@@ -60,14 +60,15 @@ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 // workgroup's LDS so that more workgroups share a CU: N = 1 by itself
 // (4 instead of 3 workgroups of 256 threads), N = 4, 7, 8 together with a
 // six-waves-per-SIMD register target (3 instead of 2, 3 instead of 2, 2
-// instead of 1). Six-wave kernels load the RK inputs in phase 3.
+// instead of 1); N = 6 needs only the register target (3 instead of 2).
+// Six-wave kernels load the RK inputs in phase 3.
 constexpr bool stage_big_euler(int DIM, int EQ, int rbytes, bool BUF)
 {
     return DIM == 3 && EQ == 1 && rbytes == 8 && BUF;
 }
 constexpr int stage_waves(int DIM, int N, int EQ, int rbytes, bool BUF)
 {
-    return stage_big_euler(DIM, EQ, rbytes, BUF) && (N == 4 || N == 7 || N == 8) ? 6 : 4;
+    return stage_big_euler(DIM, EQ, rbytes, BUF) && (N == 4 || N >= 6) ? 6 : 4;
 }
 constexpr bool stage_vel(int DIM, int N, int EQ, int rbytes, bool BUF)
 {
