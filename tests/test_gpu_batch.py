@@ -26,6 +26,12 @@ MIX = [  # (dim, N, K, eq, rk, nsteps)
     (3, 2, (4, 3, 5), EUL, 4, 3),
     (3, 4, (3, 2, 2), EUL, 4, 18),
     (3, 4, (2, 3, 1), EUL, 4, 7),  # same class: 2 x 2 tiles, ragged last row
+    # single solves of these classes use the velocity LDS layout and/or the
+    # six-wave register target, the batch kernel the tensor layout: bitwise
+    (3, 1, (40, 3, 2), EUL, 4, 3),
+    (3, 6, (2, 2, 1), EUL, 3, 2),
+    (3, 7, (2, 1, 2), EUL, 4, 2),
+    (3, 8, (1, 2, 1), EUL, 4, 2),
     (1, 5, (10,), EUL, 3, 5),
     (1, 7, (1500,), ADV, 4, 27),   # 1-D, chunked: several multi-step launches
     (1, 7, (90,), ADV, 4, 9),      # same class, held whole by one workgroup
