@@ -12,15 +12,21 @@ solenoidal velocity at Mach 0.1. The state is resident in HBM before the
 timed region. Prints one JSON line:
 
   value        unknown (DOF) updates per second per RK stage:
-               unknowns * 4 stages * K / timed seconds
+               unknowns * 4 stages * K / timed seconds, from the median of
+               --repeats timed runs of K steps (timing: median, min, max)
   roofline     the stage kernel's achieved HBM bandwidth from its algorithmic
                bytes (3.5 state-array passes per launch on average: the RK4
                schedule reads/writes 2, 4, 5 and 3 arrays in its four stages)
                over its average launch time from HIP events on its stream;
                traffic = measured HBM bytes per launch from rocprofv3 counters
-               (profiles/), null when the kernel changed since they were taken
+               (profiles/), null when the kernel changed since they were taken;
+               streaming_reference = the library's streaming probe kernel on
+               arrays of the state's size with each stage's read:write mix
   cpu_baseline the CPU oracle (FP64, OpenMP) timed on this host on full-mesh
-               RK4 steps of the same workload (a bounded sample, >= 1 step)
+               RK4 steps of the same workload (a bounded sample, >= 1 step),
+               and on one thread on a slab of it; CPU model and core count
+  other_configs the other benchmark configurations (and config 4 in the other
+               precision) timed the same way in the same run
 
 --serve measures the continuous-batching server on the seeded request stream
 (1-D/2-D advection and 2-D isothermal Euler, N in 1..7, K log-uniform in
@@ -59,6 +65,10 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, AMD public specification
 # 4+5+6+7+8+9+7
 PASSES_PER_STEP = {4: 14, 3: 9, 6: 46}
 STAGES = {4: 4, 3: 3, 6: 7}
+# (arrays read, arrays written) per fused stage
+STAGE_MIX = {4: [(1, 1), (2, 2), (3, 2), (2, 1)], 3: [(1, 2), (2, 1), (2, 1)],
+             6: [(2, 2), (3, 2), (3, 2), (3, 2), (3, 2), (3, 2), (3, 1)]}
+assert all(sum(r + w for r, w in m) == PASSES_PER_STEP[k] or k == 6 for k, m in STAGE_MIX.items())
 KERNEL_SOURCES = ["paper_2510_05254_amd/csrc/dg_stage.hpp"]
 
 
@@ -90,9 +100,22 @@ def load_traffic(workload: str, precision: str, rk: int, launch_cfg):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(w, U0, dt, budget_s: float):
-    """The oracle as it stands, on the host cores, on full-mesh RK4 steps."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, U0, dt, budget_s: float, one_thread_budget_s: float):
+    """The oracle as it stands, on the host cores, on full-mesh RK4 steps; then
+    on one thread, on a slab of the same workload (the same per-element work,
+    fewer elements) so the sample stays short."""
     import oracle
+    from paper_2510_05254_amd import workloads as W
     oracle.build(force=False)
     threads = oracle.get_threads()
     steps, t0 = 0, time.perf_counter()
@@ -105,10 +128,29 @@ def cpu_baseline(w, U0, dt, budget_s: float):
             break
         if el / steps * (steps + 1) > 1.5 * budget_s:
             break
-    return {"value": w.unknowns * 4 * steps / el, "unit": "DOF-updates/s", "cores": threads,
+    rate_all = w.unknowns * 4 * steps / el
+    # one thread: the x-extent cut so one RK4 step takes about the budget
+    per_unknown = el / (w.unknowns * 4 * steps) * threads
+    kx = max(1, min(w.K[0], int(one_thread_budget_s / (per_unknown * 4 * w.unknowns / w.K[0]))))
+    w1 = W.scaled(w, (kx,) + tuple(w.K[1:]))
+    ax1 = [oracle.axis_coords(w1.N, k) for k in w1.K]
+    U1 = W.initial_state(w1, ax1)
+    oracle.set_threads(1)
+    try:
+        t1 = time.perf_counter()
+        oracle.step(w1.dim, w1.N, w1.K, w1.eq, w1.params, U1, 4, dt, 1)
+        el1 = time.perf_counter() - t1
+    finally:
+        oracle.set_threads(threads)
+    rate_one = w1.unknowns * 4 / el1
+    return {"value": rate_all, "unit": "DOF-updates/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{steps} full-mesh RK4 step(s) of {w.name} ({w.unknowns} unknowns), "
-                      f"{el:.1f} s, FP64, OpenMP over elements"}
+                      f"{el:.1f} s, FP64, OpenMP over elements on {threads} threads",
+            "one_thread": {"value": rate_one, "unit": "DOF-updates/s", "cores": 1,
+                           "sample": f"1 RK4 step of {w1.name} ({w1.unknowns} unknowns), "
+                                     f"{el1:.1f} s"},
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
 
 
 def serve_main(a):
@@ -220,7 +262,12 @@ def main():
     ap.add_argument("--config", type=int, default=4)
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--rk", type=int, choices=[3, 4, 6], default=4)
+    ap.add_argument("--repeats", type=int, default=5, help="timed repeats of --steps steps (median)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-budget-one", type=float, default=6.0,
+                    help="seconds of the one-thread oracle sample")
+    ap.add_argument("--no-others", action="store_true",
+                    help="time only the chosen configuration (no other_configs key)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve", action="store_true", help="served-stream benchmark")
     ap.add_argument("--requests", type=int, default=2000)
@@ -251,55 +298,182 @@ def main():
     from paper_2510_05254_amd import dg
     from paper_2510_05254_amd import workloads as W
 
-    w = W.config(a.config)
-    prec = dg.DG_FP64 if a.precision == "fp64" else dg.DG_FP32
-    rsize = 8 if prec == dg.DG_FP64 else 4
     torch.cuda.init()
     stream = torch.cuda.Stream()
+    prec = dg.DG_FP64 if a.precision == "fp64" else dg.DG_FP32
+    head = measure(W.config(a.config), prec, a.rk, a.steps, a.warmup, a.repeats, stream,
+                   launch_config=a.launch_config, autotune=a.autotune, keep=True)
+    w, s, U0, dt = head.pop("_keep")
+    traffic = load_traffic(w.name, a.precision, a.rk, head["_launch_cfg"])
+    head["roofline"]["traffic"] = traffic
+    stream_ref = stream_reference(w.unknowns * (8 if prec == dg.DG_FP64 else 4), a.rk, stream)
+    head["roofline"]["streaming_reference"] = stream_ref
+    copy_gbs = torch_copy_rate()
+
+    lc = head.pop("_launch_cfg")
+    out = {
+        "metric": METRIC,
+        "value": head["value"],
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == dg.DG_FP64 else "f32",
+        "data": "synthetic",
+        "config": head["config"],
+        "roofline": head["roofline"],
+        "timing": head["timing"],
+        "launch_config": {"tile_order": "plain" if lc[0] else "xcd_contiguous",
+                          "z_slab": lc[1], "halo_divisor_1d": lc[2],
+                          "x_block": lc[4], "autotuned": bool(lc[3])},
+        "nodes_per_s": head["nodes_per_s"],
+        "copy_gbps": copy_gbs,
+        "mass_drift": head["mass_drift"],
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, U0, dt, a.cpu_budget, a.cpu_budget_one)
+        out["cpu_baseline"]["gpu_over_cpu"] = head["value"] / out["cpu_baseline"]["value"]
+    s.close()
+    del s
+    # the other benchmark configurations (and the other precision of config 4)
+    # in the same run, default launch configuration, same timing protocol
+    if not a.no_others:
+        others = {}
+        todo = [(c, "fp64") for c in (1, 2, 3, 4) if c != a.config] + \
+               [(4, "fp32" if a.precision == "fp64" else "fp64")]
+        for cid, pname in todo:
+            if (cid, pname) == (a.config, a.precision):
+                continue
+            r = measure(W.config(cid), dg.DG_FP64 if pname == "fp64" else dg.DG_FP32, a.rk,
+                        max(a.steps, 20) if cid > 1 else 2316, a.warmup, a.repeats, stream)
+            r.pop("_launch_cfg")
+            others[f"config{cid}_{pname}"] = {
+                "workload": r["config"]["workload"], "precision": pname, "value": r["value"],
+                "unit": "DOF-updates/s", "ms_per_step": r["ms_per_step"], "timing": r["timing"],
+                "roofline": {k: r["roofline"][k] for k in ("bound", "achieved", "peak", "unit", "frac",
+                                                           "alg_bytes_per_launch", "avg_launch_us")},
+                "mass_drift": r["mass_drift"]}
+        out["other_configs"] = others
+    print(json.dumps(out), flush=True)
+
+
+def measure(w, prec, rk, steps, warmup, repeats, stream, launch_config=None, autotune=False, keep=False):
+    """Time `repeats` runs of `steps` RK steps of workload w (state resident in
+    HBM, HIP events on the solver's stream); median, min and max per step."""
+    import torch
+    from paper_2510_05254_amd import dg
+    from paper_2510_05254_amd import workloads as W
+    rsize = 8 if prec == dg.DG_FP64 else 4
     s = dg.Solver(w.dim, w.N, w.K, w.eq, w.params, precision=prec, hip_stream=stream.cuda_stream)
     ax = s.axis_coords()
-    t0 = time.perf_counter()
     U0 = W.initial_state(w, ax)
     dt, _ = W.time_step(w, ax, U0)
-    t_ic = time.perf_counter() - t0
     s.set_state(U0)
     m0 = s.mass()
-    # launch configuration: the default, or autotuned before the timed region
-    # (every candidate computes the same results)
-    if a.launch_config:
-        order, slab, xblk = (int(x) for x in a.launch_config.split(","))
+    if launch_config:
+        order, slab, xblk = (int(x) for x in launch_config.split(","))
         c = list(s.launch_config())
         c[0], c[1], c[4] = order, slab, xblk
         s.set_launch_config(c)
-    launch_cfg = s.autotune(a.rk, dt, 3) if a.autotune else s.launch_config()
-
-    s.step(a.rk, dt, a.warmup)
+    lc = s.autotune(rk, dt, 3) if autotune else s.launch_config()
+    s.step(rk, dt, warmup)
     s.synchronize()
     torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    s.step(a.rk, dt, a.steps)
-    ev1.record(stream)
-    ev1.synchronize()
+    times = []
+    for _ in range(repeats):
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        s.step(rk, dt, steps)
+        ev1.record(stream)
+        ev1.synchronize()
+        times.append(ev0.elapsed_time(ev1))
     torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
     m1 = s.mass()
     Ufin = s.get_state()
     if not np.all(np.isfinite(Ufin)):
-        print("non-finite state after the timed steps", file=sys.stderr)
+        print(f"non-finite state after the timed steps of {w.name}", file=sys.stderr)
         sys.exit(1)
     del Ufin
-
-    stages = STAGES[a.rk]
-    launches = stages * a.steps
-    ms_step = ms / a.steps
-    value = w.unknowns * stages * a.steps / (ms / 1e3)
+    ms = float(np.median(times))
+    stages = STAGES[rk]
+    launches = stages * steps
+    value = w.unknowns * stages * steps / (ms / 1e3)
     avg_launch_s = ms / 1e3 / launches
-    alg_bytes = PASSES_PER_STEP[a.rk] / stages * w.unknowns * rsize
+    alg_bytes = PASSES_PER_STEP[rk] / stages * w.unknowns * rsize
     achieved = alg_bytes / avg_launch_s / 1e9
-    traffic = load_traffic(w.name, a.precision, a.rk, launch_cfg)
+    r = {
+        "value": value,
+        "ms_per_step": ms / steps,
+        "timing": {"repeats": repeats, "steps_per_repeat": steps,
+                   "ms_per_step_median": ms / steps, "ms_per_step_min": min(times) / steps,
+                   "ms_per_step_max": max(times) / steps},
+        "config": {"workload": w.name, "dim": w.dim, "N": w.N, "K": list(w.K),
+                   "equation": "advection" if w.eq == 0 else "isothermal_euler",
+                   "rk": rk, "unknowns": w.unknowns, "nodes": w.nodes, "dt": dt,
+                   "precision": "fp64" if prec == dg.DG_FP64 else "fp32"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "stage_kernel" if w.dim > 1 or rk == 6 else "ms1_kernel",
+                     "alg_bytes_per_launch": alg_bytes, "avg_launch_us": avg_launch_s * 1e6},
+        "nodes_per_s": w.nodes * stages * steps / (ms / 1e3),
+        "mass_drift": float((np.abs(m1 - m0) / np.maximum(np.abs(m0), 1.0)).max()),
+        "_launch_cfg": lc,
+    }
+    if w.dim == 1 and rk in (3, 4):
+        # temporally blocked: several steps per launch, bound by ALU/LDS, not HBM
+        r["roofline"].update({"bound": "latency", "achieved": None, "frac": None, "avg_launch_us": None,
+                              "note": "1-D steps run temporally blocked (several steps per launch, "
+                                      "arrays in LDS): neither HBM nor a per-stage launch sets the time"})
+    if keep:
+        r["_keep"] = (w, s, U0, dt)
+    else:
+        s.close()
+    return r
 
-    # achievable bandwidth: a plain device-to-device copy of 2 GiB
+
+def stream_reference(array_bytes, rk, stream, repeats=5):
+    """Achievable streaming rate for the stage schedule's read:write mix: the
+    library's probe kernel on arrays of the state's size, each stage's
+    (reads, writes) launched `repeats` times; rate = bytes of one pass over
+    the schedule / sum of the stages' median launch times."""
+    import torch
+    from paper_2510_05254_amd import dg
+    mix = STAGE_MIX[rk]
+    nbytes = (array_bytes // 16) * 16
+    bufs = [torch.empty(nbytes, dtype=torch.uint8, device="cuda") for _ in range(5)]
+    for b in bufs:
+        b.fill_(0)
+    torch.cuda.synchronize()
+    total_ms, total_bytes, per = 0.0, 0, []
+    for nin, nout in mix:
+        ins, outs = bufs[:nin], bufs[3:3 + nout]
+        dg.dg_bandwidth_probe(stream.cuda_stream, ins, outs, nbytes)     # warm-up
+        ts = []
+        for _ in range(repeats):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            dg.dg_bandwidth_probe(stream.cuda_stream, ins, outs, nbytes)
+            e1.record(stream)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        t = float(np.median(ts))
+        total_ms += t
+        total_bytes += (nin + nout) * nbytes
+        per.append({"reads": nin, "writes": nout, "ms": t, "gbps": (nin + nout) * nbytes / (t / 1e3) / 1e9})
+    del bufs
+    torch.cuda.synchronize()
+    gbps = total_bytes / (total_ms / 1e3) / 1e9
+    return {"kernel": "probe_kernel (dg_bandwidth_probe)", "gbps": gbps, "frac_of_peak": gbps / HBM_PEAK_GBS,
+            "array_bytes": nbytes, "stages": per}
+
+
+def torch_copy_rate():
+    """A plain device-to-device torch copy of 2 GiB (context)."""
+    import torch
     src = torch.empty(1 << 28, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
     dst.copy_(src)
@@ -310,44 +484,7 @@ def main():
         dst.copy_(src)
     c1.record()
     c1.synchronize()
-    copy_gbs = 5 * 2 * src.numel() * 8 / (c0.elapsed_time(c1) / 1e3) / 1e9
-    del src, dst
-
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "DOF-updates/s",
-        "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if prec == dg.DG_FP64 else "f32",
-        "data": "synthetic",
-        "config": {"workload": w.name, "dim": w.dim, "N": w.N, "K": list(w.K),
-                   "equation": "advection" if w.eq == 0 else "isothermal_euler",
-                   "rk": a.rk, "unknowns": w.unknowns, "nodes": w.nodes, "dt": dt,
-                   "precision": a.precision},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic,
-                     "kernel": "stage_kernel", "alg_bytes_per_launch": alg_bytes,
-                     "avg_launch_us": avg_launch_s * 1e6},
-        "launch_config": {"tile_order": "plain" if launch_cfg[0] else "xcd_contiguous",
-                          "z_slab": launch_cfg[1], "halo_divisor_1d": launch_cfg[2],
-                          "x_block": launch_cfg[4], "autotuned": bool(launch_cfg[3])},
-        "nodes_per_s": w.nodes * stages * a.steps / (ms / 1e3),
-        "copy_gbps": copy_gbs,
-        "mass_drift": (np.abs(m1 - m0) / np.maximum(np.abs(m0), 1.0)).max(),
-        "ic_seconds": t_ic,
-    }
-    if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, U0, dt, a.cpu_budget)
-        out["cpu_baseline"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
-    s.close()
-    print(json.dumps(out), flush=True)
+    return 5 * 2 * src.numel() * 8 / (c0.elapsed_time(c1) / 1e3) / 1e9
 
 
 if __name__ == "__main__":

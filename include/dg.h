@@ -73,6 +73,13 @@ enum dg_precision { DG_FP64 = 0, DG_FP32 = 1 };
 #define DG_MAX_ORDER 8   /* polynomial degree N ranges over 1..DG_MAX_ORDER */
 
 /* Create a solver on the current HIP device, FP64, own stream, own memory.
+ * Defining passages: the element partition of the periodic domain and the
+ * map from the reference element (Sec. 2.1, eq. transformation), N+1 LGL
+ * nodes per direction (Sec. 2.1 node definition, eqs. lagrange_pol and
+ * lag_coefs), the fluxes of eqs. advection1d/advection2d (advection) and
+ * eulerIso2d (isothermal Euler, restricted to (rho, rho u_x) in 1-D and
+ * extended by rho u_z in 3-D), the Lax-Friedrichs flux of eq. LF, periodic
+ * boundaries (Sec. 3.1).
  *   dim       1, 2 or 3
  *   N         polynomial degree, 1..8 (N+1 LGL nodes per direction)
  *   K         K[0..dim-1] >= 1, elements per direction (K[d] = 1 is its own
@@ -85,7 +92,7 @@ enum dg_precision { DG_FP64 = 0, DG_FP32 = 1 };
 int dg_create(int dim, int N, const int64_t *K, int equation, const double *params,
               dg_solver **out);
 
-/* dg_create with options:
+/* dg_create with options (same method and passages as dg_create):
  *   precision        DG_FP64 or DG_FP32 (state, RHS and stage updates in that
  *                    type; L2 and mass reductions always accumulate in FP64)
  *   hip_stream       a hipStream_t to run on, or NULL for a library stream
@@ -99,38 +106,75 @@ int dg_create_ex(int dim, int N, const int64_t *K, int equation, const double *p
                  int precision, void *hip_stream, void *device_workspace,
                  size_t workspace_bytes, dg_solver **out);
 
-/* Device bytes a solver needs to step with scheme rk (3, 4 or 6). */
+/* Device bytes a solver needs to step with scheme rk (3, 4 or 6): the
+ * operator tables plus the state and the Runge-Kutta work arrays of the
+ * scheme's stage schedule (Sec. 2.3, eqs. RK3, RK4, RK6): four state arrays
+ * for RK3 and RK4, nine for RK6, whose seven stage vectors k_s are stored.
+ * The scheme is an argument because the two sizes differ by five state
+ * arrays (5 GB at 3-D 64^3 N = 4 FP64): a caller that will only step with
+ * RK3/RK4 need not provide RK6's storage.
+ * DG_EINVAL for an invalid mesh, equation, precision or rk, or bytes NULL. */
 int dg_workspace_bytes(int dim, int N, const int64_t *K, int equation, int precision, int rk,
                        size_t *bytes);
 
-/* Release the solver (waits for its stream). NULL is accepted. */
+/* Release the solver (waits for its stream) and the memory it owns. NULL is
+ * accepted. A solver in a batch is removed from it first. */
 int dg_destroy(dg_solver *h);
 
-/* nvar = number of conserved variables; nodes = prod(K) (N+1)^dim.
- * A state array holds nvar * nodes doubles. Either pointer may be NULL. */
+/* nvar = number of conserved variables (1 for advection, 1 + dim for
+ * isothermal Euler: eqs. advection2d, eulerIso2d); nodes = prod(K) (N+1)^dim
+ * (N+1 LGL nodes per direction per element, Sec. 2.1). A state array holds
+ * nvar * nodes doubles. Either pointer may be NULL. */
 int dg_sizes(const dg_solver *h, int *nvar, int64_t *nodes);
 
-/* Node coordinates along one axis: x[e*(N+1) + i], count = K[axis] (N+1). */
+/* Node coordinates along one axis: x[e*(N+1) + i] = e dx + (dx/2)(xi_i + 1),
+ * dx = 1/K[axis], xi_i the LGL nodes (Sec. 2.1 partition, eq. transformation
+ * with the element offset), count = K[axis] (N+1). DG_EINVAL for a bad axis
+ * or count. */
 int dg_get_axis_coords(const dg_solver *h, int axis, double *x, int64_t count);
 
-/* Copy a host state (canonical layout, count = nvar * nodes doubles) in.
- * Synchronous with respect to the host buffer; stream-ordered on the device. */
+/* Node coordinates of every node: xyz[d * nodes + e * Np + n] is coordinate d
+ * of node n of element e in the canonical layout above (the tensor product of
+ * dg_get_axis_coords), count = dim * nodes doubles, host array owned by the
+ * caller (Sec. 2.1 partition, eq. transformation). DG_EINVAL for a NULL
+ * pointer or a count mismatch. */
+int dg_get_coords(const dg_solver *h, double *xyz, int64_t count);
+
+/* Copy a host state (canonical layout, count = nvar * nodes doubles) in: the
+ * nodal values U_v(x_n) of the conserved variables (Sec. 2.1, the nodal
+ * representation of eq. lagrange_pol). Synchronous with respect to the host
+ * buffer; stream-ordered on the device. In FP32 solvers the values are
+ * rounded to single precision. DG_EINVAL on a count mismatch, DG_ESTATE for a
+ * batch member. */
 int dg_set_state(dg_solver *h, const double *u, int64_t count);
 
-/* As dg_set_state from a device array of count doubles (stream-ordered; the
- * caller keeps it alive until the solver's stream has passed this point). */
+/* As dg_set_state (the nodal values of Sec. 2.1) from a device array of count
+ * FP64 values (stream-ordered; the caller keeps it alive until the solver's
+ * stream has passed this point). DG_EINVAL on a count mismatch, DG_ESTATE for
+ * a batch member. */
 int dg_set_state_device(dg_solver *h, const void *u_dev, int64_t count);
 
-/* Advance nsteps steps of size dt with scheme rk (DG_RK3, DG_RK4, DG_RK6).
- * Asynchronous: enqueues nsteps * stages kernel launches on the solver's
- * stream and returns. dt must be finite and > 0, nsteps >= 0 (0 is a no-op).
- * DG_ESTATE before the first set_state. No blow-up check is made. */
+/* Advance nsteps steps of size dt with scheme rk (DG_RK3, DG_RK4, DG_RK6) of
+ * the semi-discrete system dU/dt = R(U) (Sec. 2.3, eqs. RK3 -- read as Heun's
+ * third-order method --, RK4, RK6), where R is the NDG right-hand side of the
+ * weak-form evolution equation of Sec. 2.1 (volume term with the LGL
+ * differentiation matrix, Lax-Friedrichs flux of eq. LF at the faces, lift
+ * by the lumped mass of eq. lag_coefs), evaluated on every element of the
+ * periodic mesh. Asynchronous: enqueues the stage kernel launches on the
+ * solver's stream and returns. dt must be finite and > 0, nsteps >= 0 (0 is a
+ * no-op). DG_EINVAL for a bad rk/dt/nsteps, DG_ESTATE before the first
+ * set_state or for a batch member, DG_ENOMEM when RK6 storage cannot be had.
+ * No blow-up check is made. */
 int dg_step(dg_solver *h, int rk, double dt, int64_t nsteps);
 
-/* Copy the current state out (waits for the stream). count = nvar * nodes. */
+/* Copy the current state out (waits for the stream). count = nvar * nodes,
+ * canonical layout, host array owned by the caller. DG_EINVAL on a count
+ * mismatch, DG_ESTATE before the first set_state. */
 int dg_get_state(dg_solver *h, double *u, int64_t count);
 
-/* As dg_get_state into a device array of count doubles (stream-ordered). */
+/* As dg_get_state (the nodal values of Sec. 2.1) into a device array of count
+ * FP64 values (stream-ordered). DG_EINVAL on a count mismatch, DG_ESTATE
+ * before the first set_state. */
 int dg_get_state_device(dg_solver *h, void *u_dev, int64_t count);
 
 /* L2 error of the current state against a host reference u_ref (canonical
@@ -143,21 +187,27 @@ int dg_get_state_device(dg_solver *h, void *u_dev, int64_t count);
 int dg_l2_error(dg_solver *h, const double *u_ref, int64_t count, double *abs_err,
                 double *rel_err);
 
-/* Per-variable squared L2 norms: sq_err[v] = integral (U_v - Uref_v)^2 and
- * sq_ref[v] = integral Uref_v^2 (arrays of nvar doubles). */
+/* Per-variable squared L2 norms (Sec. 3.1 L2 norm, nodal LGL quadrature with
+ * the element Jacobian): sq_err[v] = integral (U_v - Uref_v)^2 and
+ * sq_ref[v] = integral Uref_v^2 (arrays of nvar doubles). FP64; waits. */
 int dg_l2_error_vars(dg_solver *h, const double *u_ref, int64_t count, double *sq_err,
                      double *sq_ref);
 
-/* mass[v] = integral of U_v over the domain (nvar doubles), FP64; waits. */
+/* mass[v] = integral of U_v over the domain (nvar doubles) with the nodal
+ * LGL quadrature of the lumped mass (eq. lag_coefs; the conserved integral
+ * of the conservation law of Sec. 2.1, eq. scalar_cons), FP64; waits. */
 int dg_mass(dg_solver *h, double *mass);
 
-/* Wait for all work enqueued on the solver's stream. */
+/* Wait for all work enqueued on the solver's stream (no computation). */
 int dg_synchronize(dg_solver *h);
 
-/* The solver's hipStream_t (as void*), for stream-ordered interop. */
+/* The solver's hipStream_t (as void*), for stream-ordered interop; NULL for
+ * a NULL handle. */
 void *dg_stream(const dg_solver *h);
 
-/* Autotune the launch configuration for stepping h with scheme rk and step
+/* Autotune the launch configuration (no change to the method: every
+ * candidate evaluates the same Sec. 2.1 right-hand side and Sec. 2.3 scheme
+ * bit for bit) for stepping h with scheme rk and step
  * dt: times trial_steps (1..1000) steps of each candidate on the solver's
  * arrays, restarting from a saved copy of the state, restores the state and
  * keeps the fastest candidate for later dg_step calls. Candidates: 3-D, the
@@ -190,7 +240,10 @@ int dg_set_launch_config(dg_solver *h, const int64_t *cfg, int n);
 
 /* ---------------------------------------------------------------------------
  * Batched stepping (many solves advanced together; the method per solve is
- * unchanged: every member takes the same RK steps it would take alone).
+ * unchanged: every member takes the same Sec. 2.3 RK steps of the Sec. 2.1
+ * right-hand side it would take alone). Small grids leave a GPU mostly idle
+ * (the paper's Sec. 3.2 finds GPUs efficient only from about 1e6-1e7 degrees
+ * of freedom), so many small solves share each launch.
  *
  * A batch advances its member solvers on the batch's stream. Each "tick" is
  * one RK step of every active member; all members that share a kernel class
@@ -222,7 +275,8 @@ int dg_batch_add(dg_batch *b, dg_solver *h, int rk, double dt, int64_t nsteps);
 /* Remove member h (finished or not); its remaining steps are dropped. */
 int dg_batch_remove(dg_batch *b, dg_solver *h);
 
-/* Enqueue s = min(max_steps, smallest remaining step count of the active
+/* Enqueue (Sec. 2.3 steps of every active member) s = min(max_steps,
+ * smallest remaining step count of the active
  * members) ticks and return s in *steps_done (0 when no member is active).
  * Members whose remaining count reaches 0 become inactive (they stay members
  * until removed). Asynchronous. */
@@ -237,7 +291,24 @@ int dg_batch_size(const dg_batch *b, int *members, int *active);
 /* Wait for all work enqueued on the batch's stream. */
 int dg_batch_synchronize(dg_batch *b);
 
-/* Message for the calling thread's last non-OK return ("" if none). */
+/* ---------------------------------------------------------------------------
+ * Measurement helper (no part of the method).
+ * ------------------------------------------------------------------------ */
+
+/* Streaming bandwidth reference: one launch on hip_stream (NULL = the null
+ * stream) that reads nin (1..3) device arrays and writes nout (1..2) device
+ * arrays of `bytes` bytes each (a positive multiple of 16; 16-byte aligned
+ * pointers, owned by the caller): out_o[i] = sum_j in_j[i] + o over pairs of
+ * doubles, one coalesced 16-byte access per thread and array. Timing the four
+ * (nin, nout) mixes of a fused RK4 stage schedule on arrays of the state's
+ * size gives the rate plain streaming of the stage kernels' algorithmic bytes
+ * reaches (the roofline reference beside the HBM peak). Asynchronous.
+ * DG_EINVAL on a bad count, size, NULL or misaligned pointer. */
+int dg_bandwidth_probe(void *hip_stream, const void *const *in, int nin, void *const *out,
+                       int nout, int64_t bytes);
+
+/* Message for the calling thread's last non-OK return ("" if none). Owned by
+ * the library, valid until the thread's next failing call. */
 const char *dg_last_error(void);
 
 #ifdef __cplusplus

@@ -660,6 +660,32 @@ int dg_get_axis_coords(const dg_solver *h, int axis, double *x, int64_t count)
     return DG_OK;
 }
 
+int dg_get_coords(const dg_solver *h, double *xyz, int64_t count)
+{
+    if (!h || !xyz) return fail(DG_EINVAL, "NULL argument");
+    if (count != (int64_t)h->dim * h->nodes) return fail(DG_EINVAL, "count must be dim * nodes");
+    // per-axis coordinates, then the tensor product in the canonical order
+    std::vector<double> ax[3];
+    for (int d = 0; d < h->dim; ++d) {
+        ax[d].resize(h->K[d] * h->n1);
+        int rc = dg_get_axis_coords(h, d, ax[d].data(), (int64_t)ax[d].size());
+        if (rc) return rc;
+    }
+    const int n1 = h->n1;
+    int64_t node = 0;
+    for (int64_t ez = 0; ez < h->K[2]; ++ez)
+        for (int64_t ey = 0; ey < h->K[1]; ++ey)
+            for (int64_t ex = 0; ex < h->K[0]; ++ex)
+                for (int k = 0; k < (h->dim > 2 ? n1 : 1); ++k)
+                    for (int j = 0; j < (h->dim > 1 ? n1 : 1); ++j)
+                        for (int i = 0; i < n1; ++i, ++node) {
+                            xyz[node] = ax[0][ex * n1 + i];
+                            if (h->dim > 1) xyz[h->nodes + node] = ax[1][ey * n1 + j];
+                            if (h->dim > 2) xyz[2 * h->nodes + node] = ax[2][ez * n1 + k];
+                        }
+    return DG_OK;
+}
+
 int dg_set_state(dg_solver *h, const double *u, int64_t count)
 {
     if (!h || !u) return fail(DG_EINVAL, "NULL argument");

@@ -34,6 +34,7 @@ SIGNATURES = {
     "dg_destroy": (_I, [_P]),
     "dg_sizes": (_I, [_P, _P, _P]),
     "dg_get_axis_coords": (_I, [_P, _I, _P, _I64]),
+    "dg_get_coords": (_I, [_P, _P, _I64]),
     "dg_set_state": (_I, [_P, _P, _I64]),
     "dg_set_state_device": (_I, [_P, _P, _I64]),
     "dg_step": (_I, [_P, _I, _D, _I64]),
@@ -56,6 +57,7 @@ SIGNATURES = {
     "dg_batch_remaining": (_I, [_P, _P, _P]),
     "dg_batch_size": (_I, [_P, _P, _P]),
     "dg_batch_synchronize": (_I, [_P]),
+    "dg_bandwidth_probe": (_I, [_P, _P, _I, _P, _I, _I64]),
 }
 DG_BATCH_GRAPH = 1
 
@@ -171,6 +173,13 @@ def dg_get_axis_coords(h, axis, K_axis, N):
     return x
 
 
+def dg_get_coords(h, dim, nodes):
+    """Node coordinates, shape (dim, nodes), canonical node order."""
+    x = np.zeros((int(dim), int(nodes)))
+    _call("dg_get_coords", h, _ptr(x), x.size)
+    return x
+
+
 def dg_set_state(h, u):
     u = np.ascontiguousarray(u, dtype=np.float64)
     _call("dg_set_state", h, _ptr(u), u.size)
@@ -250,6 +259,15 @@ def dg_stream(h) -> int:
     return load().dg_stream(h) or 0
 
 
+def dg_bandwidth_probe(hip_stream, ins, outs, nbytes):
+    """Streaming reference launch: reads the device arrays `ins`, writes `outs`
+    (integer addresses or tensors), `nbytes` bytes each."""
+    ia = (ctypes.c_void_p * len(ins))(*[_dev_ptr_any(x).value for x in ins])
+    oa = (ctypes.c_void_p * len(outs))(*[_dev_ptr_any(x).value for x in outs])
+    _call("dg_bandwidth_probe", ctypes.c_void_p(hip_stream) if hip_stream else None, ia, len(ins), oa,
+          len(outs), int(nbytes))
+
+
 def dg_last_error() -> str:
     return load().dg_last_error().decode()
 
@@ -289,6 +307,9 @@ class Solver:
 
     def axis_coords(self):
         return [dg_get_axis_coords(self.h, d, self.K[d], self.N) for d in range(self.dim)]
+
+    def coords(self):
+        return dg_get_coords(self.h, self.dim, self.nodes)
 
     def set_state(self, u):
         dg_set_state(self.h, u)

@@ -6,6 +6,19 @@ from paper_2510_05254_amd import workloads as W
 
 ADV, EUL = 0, 1
 PARITY_RTOL = 1e-12          # FP64 GPU vs oracle, relative L2 per variable
+# Elementwise companion of the L2 bar: per variable v,
+#   max_n |U_gpu[v,n] - U_oracle[v,n]| <= ELEM_C * PARITY_RTOL * max_n |U_oracle[v,n]|.
+# The two sides differ by rounding only (FMA contraction, the refined
+# reciprocal, strong vs weak form), a few units of u = 1.1e-16 of the node's
+# operand scale per stage operation. After s stages the worst node stays below
+# s * (a few tens) * u of the variable's scale, i.e. below 1e-12 for s <= 800
+# (the longest fixed-step configuration: 200 RK4 steps) whenever the operand
+# scale does not exceed the variable's own scale by more than ~10 (momenta at
+# Mach 0.1 carry rho c^2 ~ 10 max|m| in their fluxes). ELEM_C = 1 therefore
+# leaves the bar where the L2 bar is, but catches an error confined to a few
+# nodes (a face point, a lift slot, a tile edge) that the L2 norm dilutes by
+# sqrt(nodes).
+ELEM_C = 1.0
 
 
 def epb(dim, N):
@@ -40,6 +53,25 @@ def case(dim, N, K, eq, seed=1234, **ic):
     U0 = W.initial_state(w, ax)
     dt = 0.1 * W.dx_min(ax) / sum(W.max_speeds(w, U0))
     return w, ax, U0, dt
+
+
+def max_rel_per_var(A, B):
+    """max_n |A[v,n] - B[v,n]| / max_n |B[v,n]| per variable."""
+    A = np.asarray(A).reshape(B.shape[0], -1)
+    B = np.asarray(B).reshape(B.shape[0], -1)
+    return np.array([np.max(np.abs(A[v] - B[v])) / max(np.max(np.abs(B[v])), 1e-300)
+                     for v in range(B.shape[0])])
+
+
+def parity(Ug, Uo, rtol=PARITY_RTOL, what=""):
+    """Assert the FP64 parity bar, relative L2 and elementwise, per variable;
+    return (l2, elementwise) for printing."""
+    l2 = rel_l2_per_var(Ug, Uo)
+    el = max_rel_per_var(Ug, Uo)
+    assert np.all(np.isfinite(np.asarray(Ug))), f"{what}: non-finite GPU result"
+    assert np.all(l2 <= rtol), f"{what}: rel L2 per var {l2} > {rtol}"
+    assert np.all(el <= ELEM_C * rtol), f"{what}: max abs err / max |U| per var {el} > {ELEM_C * rtol}"
+    return l2, el
 
 
 def rel_l2_per_var(A, B):

@@ -80,9 +80,22 @@ def test_null_handle_calls_fail_cleanly():
     lib = dg.load()
     assert lib.dg_step(None, 4, 0.1, 1) == dg.DG_EINVAL
     assert lib.dg_sizes(None, None, None) == dg.DG_EINVAL
+    assert lib.dg_get_coords(None, None, 0) == dg.DG_EINVAL
     assert lib.dg_destroy(None) == dg.DG_OK
     assert lib.dg_stream(None) is None
     assert "NULL" in dg.dg_last_error() or dg.dg_last_error() == ""
+
+
+def test_bandwidth_probe_validates_arguments():
+    lib = dg.load()
+    arr = (ctypes.c_void_p * 3)(16, 32, 48)
+    assert lib.dg_bandwidth_probe(None, arr, 0, arr, 1, 1024) == dg.DG_EINVAL
+    assert lib.dg_bandwidth_probe(None, arr, 4, arr, 1, 1024) == dg.DG_EINVAL
+    assert lib.dg_bandwidth_probe(None, arr, 1, arr, 3, 1024) == dg.DG_EINVAL
+    assert lib.dg_bandwidth_probe(None, arr, 1, arr, 1, 1000) == dg.DG_EINVAL
+    assert lib.dg_bandwidth_probe(None, None, 1, arr, 1, 1024) == dg.DG_EINVAL
+    bad = (ctypes.c_void_p * 1)(8)
+    assert lib.dg_bandwidth_probe(None, bad, 1, arr, 1, 1024) == dg.DG_EINVAL
 
 
 def test_workspace_bytes():

@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 from paper_2510_05254_amd import dg
-from _helpers import ADV, EUL, PARITY_RTOL, case, params, ragged_K, rel_l2_per_var
+from _helpers import ADV, EUL, PARITY_RTOL, case, params, parity, ragged_K, rel_l2_per_var
 
 pytestmark = pytest.mark.gpu
 
@@ -32,8 +32,7 @@ def _run_both(dim, N, K, eq, rk, nsteps, seed=1234):
 def test_parity_rk4(dim, N, eq):
     K = ragged_K(dim, N)
     U0, Ug, Uo = _run_both(dim, N, K, eq, 4, 3)
-    err = rel_l2_per_var(Ug, Uo)
-    assert np.all(err <= PARITY_RTOL), err
+    parity(Ug, Uo, what=f"dim={dim} N={N} eq={eq} K={K}")
     assert rel_l2_per_var(Uo, U0).max() > 1e3 * PARITY_RTOL     # the state really moved
 
 
@@ -42,7 +41,7 @@ def test_parity_rk4(dim, N, eq):
 def test_parity_rk3_rk6(dim, N, eq, rk):
     K = ragged_K(dim, N)
     U0, Ug, Uo = _run_both(dim, N, K, eq, rk, 2)
-    assert np.all(rel_l2_per_var(Ug, Uo) <= PARITY_RTOL)
+    parity(Ug, Uo, what=f"rk={rk} dim={dim} N={N} eq={eq}")
 
 
 @pytest.mark.parametrize("dim,N,K,eq", [
@@ -57,7 +56,7 @@ def test_parity_rk3_rk6(dim, N, eq, rk):
 ])
 def test_parity_special_meshes(dim, N, K, eq):
     U0, Ug, Uo = _run_both(dim, N, K, eq, 4, 2)
-    assert np.all(rel_l2_per_var(Ug, Uo) <= PARITY_RTOL)
+    parity(Ug, Uo, what=f"dim={dim} N={N} K={K} eq={eq}")
 
 
 # 1-D RK3/RK4 run temporally blocked (several steps per launch, arrays in
@@ -77,7 +76,7 @@ def test_parity_1d_chunked_multistep(N, K, eq, rk, nsteps):
         Ug = s.get_state()
         m1 = s.mass()
     Uo = oracle.step(1, N, (K,), eq, params(1, eq), U0, rk, dt, nsteps)
-    assert np.all(rel_l2_per_var(Ug, Uo) <= PARITY_RTOL)
+    parity(Ug, Uo, what=f"1-D N={N} K={K} eq={eq} rk={rk}")
     assert rel_l2_per_var(Uo, U0).max() > 1e3 * PARITY_RTOL
     scale = np.abs(U0).reshape(U0.shape[0], -1).max(axis=1)
     assert np.all(np.abs(m1 - m0) <= 1e-14 * np.maximum(scale, 1.0))
@@ -96,6 +95,7 @@ def test_parity_1d_whole_mesh_many_steps():
         Ug = s.get_state()
     Uo = oracle.step(1, N, K, eq, params(1, eq), U0, 4, dt, 4100)
     assert np.linalg.norm(Ug - Uo) <= PARITY_RTOL * np.linalg.norm(U0)
+    assert np.max(np.abs(Ug - Uo)) <= PARITY_RTOL * np.max(np.abs(U0))
     assert np.linalg.norm(Uo) < 0.1 * np.linalg.norm(U0)        # the long run really happened
 
 
@@ -157,6 +157,23 @@ def test_axis_coords_and_roundtrip(dim, N, K):
     with dg.Solver(dim, N, K, EUL, (1.0,)) as s:
         for d, x in enumerate(s.axis_coords()):
             np.testing.assert_allclose(x, oracle.axis_coords(N, K[d]), rtol=0, atol=4.5e-16)
+        # all node coordinates: the tensor product of the oracle's per-axis
+        # coordinates in the canonical (element x fastest, node x fastest) order
+        xyz = s.coords()
+        assert xyz.shape == (dim, s.nodes)
+        oax = [oracle.axis_coords(N, K[d]).reshape(K[d], N + 1) for d in range(dim)]
+        n1 = N + 1
+        for node in np.random.default_rng(3).integers(0, s.nodes, 200).tolist() + [0, s.nodes - 1]:
+            e, n = divmod(node, n1 ** dim)
+            ee, nn = [], []
+            for d in range(dim):
+                ee.append(e % K[d]); e //= K[d]
+                nn.append(n % n1); n //= n1
+            for d in range(dim):
+                assert abs(xyz[d, node] - oax[d][ee[d], nn[d]]) <= 4.5e-16, (node, d)
+        with pytest.raises(dg.DgError) as e:
+            dg._call("dg_get_coords", s.h, np.zeros(3).ctypes.data_as(dg.ctypes.c_void_p), 3)
+        assert e.value.status == dg.DG_EINVAL
         U = np.random.default_rng(1).standard_normal((s.nvar, s.nodes))
         s.set_state(U)
         np.testing.assert_array_equal(s.get_state(), U)
@@ -200,7 +217,7 @@ def test_device_arrays_stream_and_workspace():
         s.synchronize()
         Ug = out.cpu().numpy()
     Uo = oracle.step(dim, N, K, eq, params(dim, eq), U0, 6, dt, 2)
-    assert np.all(rel_l2_per_var(Ug, Uo) <= PARITY_RTOL)
+    parity(Ug, Uo, what="device arrays, external stream and workspace, RK6")
 
 
 def test_workspace_too_small_for_rk6():
