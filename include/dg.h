@@ -292,6 +292,48 @@ int dg_batch_size(const dg_batch *b, int *members, int *active);
 int dg_batch_synchronize(dg_batch *b);
 
 /* ---------------------------------------------------------------------------
+ * Stepping without device allocation.
+ * ------------------------------------------------------------------------ */
+
+/* Bytes of the fixed device array dg_step_static takes its work memory from
+ * (one array per GPU the library runs on, held until the process ends). */
+#define DG_STATIC_SCRATCH_BYTES (128u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): dg_step on
+ * a device state the caller holds, with no solver handle and no device
+ * allocation by the library (no hipMalloc, hipFree or allocating library
+ * routine on any path).
+ *   dim, N, K, equation, params, precision   as dg_create_ex
+ *   hip_stream   hipStream_t to run on, or NULL for the null stream
+ *   u_dev        device array of count = nvar * nodes values in the state
+ *                precision (double for DG_FP64, float for DG_FP32),
+ *                canonical layout, aligned to its element size; advanced in
+ *                place. Owned by the caller.
+ *   rk, dt, nsteps   as dg_step (DG_RK3, DG_RK4, DG_RK6; nsteps 0 is a no-op)
+ * Work memory: the operator tables and the Runge-Kutta work arrays (3 state
+ * arrays for RK3/RK4, 8 for RK6) come from the library's fixed device array
+ * of DG_STATIC_SCRATCH_BYTES bytes on the current device. A problem needing
+ * more gives DG_ENOMEM, with the bytes needed in dg_last_error() (limit for
+ * RK4: about DG_STATIC_SCRATCH_BYTES / 3 bytes per state array, e.g. 2-D
+ * advection 256^2 N = 7 in FP64).
+ * Asynchronous like dg_step, except that a call whose (dim, N, precision)
+ * differs from the previous call's on the same device uploads the operator
+ * tables and waits for hip_stream. Results are bitwise those of a solver made
+ * with dg_create_ex on the same arguments, given the same state and stepped
+ * with dg_step.
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind: calls whose work overlaps on one GPU (on other streams or from
+ * other host threads while earlier work is still in flight) race and give
+ * undefined results; issue them on one stream or synchronize between them.
+ * DG_EINVAL for invalid arguments (as dg_create_ex and dg_step, plus a NULL
+ * or misaligned u_dev or a count mismatch), DG_ENOTSUP for an unbuilt class,
+ * DG_EDEVICE for a HIP failure. */
+int dg_step_static(int dim, int N, const int64_t *K, int equation, const double *params,
+                   int precision, void *hip_stream, void *u_dev, int64_t count, int rk, double dt,
+                   int64_t nsteps);
+
+/* ---------------------------------------------------------------------------
  * Measurement helper (no part of the method).
  * ------------------------------------------------------------------------ */
 

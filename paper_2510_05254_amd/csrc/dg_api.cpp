@@ -264,6 +264,102 @@ MsSolve ms_solve(const dg_solver *h, int rk, double dt, const MsPlan &pl)
     return m;
 }
 
+int setup_solver(dg_solver *h, int dim, int N, const int64_t *K, int equation, const double *params,
+                 int precision)
+{
+    h->dim = dim;
+    h->N = N;
+    h->eq = equation;
+    h->prec = precision;
+    h->nvar = equation == DG_ADVECTION ? 1 : 1 + dim;
+    h->n1 = N + 1;
+    h->np = 1;
+    for (int d = 0; d < dim; ++d) h->np *= h->n1;
+    int64_t E = 1;
+    for (int d = 0; d < 3; ++d) {
+        h->K[d] = d < dim ? K[d] : 1;
+        E *= h->K[d];
+    }
+    h->nodes = E * h->np;
+    h->unknowns = h->nodes * h->nvar;
+    if (equation == DG_ADVECTION)
+        for (int d = 0; d < dim; ++d) h->par[d] = params[d];
+    else
+        h->par[0] = params[0];
+    lgl_operator(N, h->xi, h->w, h->D);
+    h->lay = layout_for(dim, N, K, equation, precision);
+    h->stage = stage_fn(precision, equation, dim, N);
+    if (!h->stage) return fail(DG_ENOTSUP, "no stage kernel built for this configuration");
+    h->epb = stage_epb(dim, N);
+    h->tiles_x = (h->K[0] + h->epb - 1) / h->epb;
+    h->epy = stage_epy(dim, N);
+    h->tiles_y = (h->K[1] + h->epy - 1) / h->epy;
+    // default 3-D tile order: x-blocks of about an eighth of the x-tiles (the
+    // largest divisor in [4, max(4, tiles_x / 8)], else whole rows), walked
+    // y-tile by y-tile, then layer by layer: each XCD's contiguous range
+    // is then an x-column of the mesh, whose y- and z-neighbour traces stay
+    // in that XCD's L2 (z-slab 1)
+    h->slab = 1;
+    h->xblk = h->tiles_x;
+    if (dim == 3) {
+        for (int64_t xb = std::max<int64_t>(4, h->tiles_x / kXcds); xb >= 4; --xb)
+            if (h->tiles_x % xb == 0) { h->xblk = xb; break; }
+    }
+    h->ntiles = h->tiles_x * h->tiles_y * h->K[2];
+    h->grid = std::min<int64_t>(h->ntiles, kMaxGrid);
+    return DG_OK;
+}
+
+char *carve_tables(dg_solver *h, char *p)
+{
+    h->Dtab = p;
+    p += round_up(sizeof(double) * kMaxNP1 * kMaxNP1);
+    h->wtab = reinterpret_cast<double *>(p);
+    p += round_up(sizeof(double) * kMaxNP1);
+    h->partial = reinterpret_cast<double *>(p);
+    p += round_up(sizeof(double) * 8 * kReduceBlocks);
+    h->ftab = reinterpret_cast<uint32_t *>(p);
+    p += round_up(kFaceTableBytes);
+    return p;
+}
+
+char *carve_rk_arrays(dg_solver *h, char *p, bool rk6)
+{
+    h->A = p;  p += h->lay.array;
+    h->Ya = p; p += h->lay.array;
+    h->Yb = p; p += h->lay.array;
+    if (rk6)
+        for (int i = 0; i < 5; ++i, p += h->lay.array) h->kx[i] = p;
+    return p;
+}
+
+int upload_tables(dg_solver *h)
+{
+    // operator tables in the state precision (D) and FP64 (w)
+    unsigned char dbuf[sizeof(double) * kMaxNP1 * kMaxNP1];
+    const int nd = h->n1 * h->n1;
+    if (h->prec == DG_FP64) {
+        std::memcpy(dbuf, h->D, sizeof(double) * nd);
+    } else {
+        float *f = reinterpret_cast<float *>(dbuf);
+        for (int i = 0; i < nd; ++i) f[i] = (float)h->D[i];
+    }
+    const size_t dbytes = (h->prec == DG_FP64 ? 8 : 4) * (size_t)nd;
+    // (host buffers on the stack: no heap allocation on this path)
+    const size_t fbytes = 16 * (size_t)face_table_size(h->dim, h->N, h->epb, h->epy);
+    if (fbytes > kFaceTableBytes) return fail(DG_ENOTSUP, "face table larger than reserved");
+    uint32_t ftab[kFaceTableBytes / 4];
+    build_face_table(h->dim, h->N, h->epb, h->epy, ftab);
+    hipError_t e;
+    if ((e = hipMemcpyAsync(h->Dtab, dbuf, dbytes, hipMemcpyHostToDevice, h->stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(h->ftab, ftab, fbytes, hipMemcpyHostToDevice, h->stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(h->wtab, h->w, sizeof(double) * h->n1, hipMemcpyHostToDevice, h->stream)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(h->stream)) != hipSuccess)
+        return hip_fail(e, "operator upload");
+    return DG_OK;
+}
+
 namespace {
 
 int launch(dg_solver *h, const StageParams &p)
@@ -407,6 +503,21 @@ int step_rk6(dg_solver *h, double dt)
     return DG_OK;
 }
 
+}  // namespace
+
+int enqueue_steps(dg_solver *h, int rk, double dt, int64_t nsteps)
+{
+    const MsPlan pl = ms_plan(h, rk);
+    if (pl.ok) return step_ms(h, rk, dt, nsteps, pl);
+    for (int64_t s = 0; s < nsteps; ++s) {
+        const int rc = rk == DG_RK6 ? step_rk6(h, dt) : step_rk34(h, rk, dt);
+        if (rc) return rc;
+    }
+    return DG_OK;
+}
+
+namespace {
+
 int check_count(const dg_solver *h, int64_t count)
 {
     if (count != h->unknowns)
@@ -502,8 +613,8 @@ int dg_create_ex(int dim, int N, const int64_t *K, int equation, const double *p
     *out = nullptr;
     int rc = validate(dim, N, K, equation, params, precision);
     if (rc) return rc;
-    StageFn fn = stage_fn(precision, equation, dim, N);
-    if (!fn) return fail(DG_ENOTSUP, "no stage kernel built for this configuration");
+    if (!stage_fn(precision, equation, dim, N))
+        return fail(DG_ENOTSUP, "no stage kernel built for this configuration");
 
     int ndev = 0;
     hipError_t e = hipGetDeviceCount(&ndev);
@@ -514,46 +625,10 @@ int dg_create_ex(int dim, int N, const int64_t *K, int equation, const double *p
 
     dg_solver *h = new (std::nothrow) dg_solver();
     if (!h) return fail(DG_ENOMEM, "host allocation failed");
-    h->dim = dim;
-    h->N = N;
-    h->eq = equation;
-    h->prec = precision;
-    h->nvar = equation == DG_ADVECTION ? 1 : 1 + dim;
-    h->n1 = N + 1;
-    h->np = 1;
-    for (int d = 0; d < dim; ++d) h->np *= h->n1;
-    int64_t E = 1;
-    for (int d = 0; d < 3; ++d) {
-        h->K[d] = d < dim ? K[d] : 1;
-        E *= h->K[d];
+    if ((rc = setup_solver(h, dim, N, K, equation, params, precision))) {
+        delete h;
+        return rc;
     }
-    h->nodes = E * h->np;
-    h->unknowns = h->nodes * h->nvar;
-    if (equation == DG_ADVECTION)
-        for (int d = 0; d < dim; ++d) h->par[d] = params[d];
-    else
-        h->par[0] = params[0];
-    lgl_operator(N, h->xi, h->w, h->D);
-    h->lay = layout_for(dim, N, K, equation, precision);
-    h->stage = fn;
-    h->epb = stage_epb(dim, N);
-    h->tiles_x = (h->K[0] + h->epb - 1) / h->epb;
-    h->epy = stage_epy(dim, N);
-    h->tiles_y = (h->K[1] + h->epy - 1) / h->epy;
-    // default 3-D tile order: x-blocks of about an eighth of the x-tiles (the
-    // largest divisor in [4, max(4, tiles_x / 8)], else whole rows), walked
-    // y-tile by y-tile, then layer by layer: each XCD's contiguous range
-    // is then an x-column of the mesh, whose y- and z-neighbour traces stay
-    // in that XCD's L2 (z-slab 1)
-    h->slab = 1;
-    h->xblk = h->tiles_x;
-    if (dim == 3) {
-        for (int64_t xb = std::max<int64_t>(4, h->tiles_x / kXcds); xb >= 4; --xb)
-            if (h->tiles_x % xb == 0) { h->xblk = xb; break; }
-    }
-    h->ntiles = h->tiles_x * h->tiles_y * h->K[2];
-    h->grid = std::min<int64_t>(h->ntiles, kMaxGrid);
-
     e = hipGetDevice(&h->device);
     if (e != hipSuccess) { delete h; return hip_fail(e, "hipGetDevice"); }
 
@@ -586,44 +661,12 @@ int dg_create_ex(int dim, int N, const int64_t *K, int equation, const double *p
         h->own_ws = true;
         h->ws_bytes = h->lay.base;
     }
-    char *p = h->ws;
-    h->Dtab = p;
-    p += round_up(sizeof(double) * kMaxNP1 * kMaxNP1);
-    h->wtab = reinterpret_cast<double *>(p);
-    p += round_up(sizeof(double) * kMaxNP1);
-    h->partial = reinterpret_cast<double *>(p);
-    p += round_up(sizeof(double) * 8 * kReduceBlocks);
-    h->ftab = reinterpret_cast<uint32_t *>(p);
-    p += round_up(kFaceTableBytes);
-    h->U = p;  p += h->lay.array;
-    h->A = p;  p += h->lay.array;
-    h->Ya = p; p += h->lay.array;
-    h->Yb = p; p += h->lay.array;
-
-    // operator tables in the state precision (D) and FP64 (w)
-    unsigned char dbuf[sizeof(double) * kMaxNP1 * kMaxNP1];
-    const int nd = h->n1 * h->n1;
-    if (precision == DG_FP64) {
-        std::memcpy(dbuf, h->D, sizeof(double) * nd);
-    } else {
-        float *f = reinterpret_cast<float *>(dbuf);
-        for (int i = 0; i < nd; ++i) f[i] = (float)h->D[i];
-    }
-    const size_t dbytes = (precision == DG_FP64 ? 8 : 4) * (size_t)nd;
-    std::vector<uint32_t> ftab(4 * (size_t)face_table_size(dim, N, h->epb, h->epy));
-    build_face_table(dim, N, h->epb, h->epy, ftab.data());
-    if (ftab.size() * 4 > kFaceTableBytes) {
+    char *arrays = carve_tables(h, h->ws);
+    h->U = arrays;
+    carve_rk_arrays(h, arrays + h->lay.array, false);
+    if ((rc = upload_tables(h))) {
         free_solver(h);
-        return fail(DG_ENOTSUP, "face table larger than reserved");
-    }
-    if ((e = hipMemcpyAsync(h->Dtab, dbuf, dbytes, hipMemcpyHostToDevice, h->stream)) != hipSuccess ||
-        (e = hipMemcpyAsync(h->ftab, ftab.data(), ftab.size() * 4, hipMemcpyHostToDevice, h->stream)) !=
-            hipSuccess ||
-        (e = hipMemcpyAsync(h->wtab, h->w, sizeof(double) * h->n1, hipMemcpyHostToDevice, h->stream)) !=
-            hipSuccess ||
-        (e = hipStreamSynchronize(h->stream)) != hipSuccess) {
-        free_solver(h);
-        return hip_fail(e, "operator upload");
+        return rc;
     }
     *out = h;
     return DG_OK;
@@ -736,13 +779,7 @@ int dg_step(dg_solver *h, int rk, double dt, int64_t nsteps)
     int rc = select_device(h);
     if (rc) return rc;
     if (rk == DG_RK6 && (rc = ensure_rk6(h))) return rc;
-    const MsPlan pl = ms_plan(h, rk);
-    if (pl.ok) return step_ms(h, rk, dt, nsteps, pl);
-    for (int64_t s = 0; s < nsteps; ++s) {
-        rc = rk == DG_RK6 ? step_rk6(h, dt) : step_rk34(h, rk, dt);
-        if (rc) return rc;
-    }
-    return DG_OK;
+    return enqueue_steps(h, rk, dt, nsteps);
 }
 
 int dg_get_state(dg_solver *h, double *u, int64_t count)

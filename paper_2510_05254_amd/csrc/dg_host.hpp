@@ -82,6 +82,25 @@ struct dg_solver {
 namespace dg {
 
 int select_device(const dg_solver *h);
+// Argument checks shared by every entry point that describes a mesh.
+int validate(int dim, int N, const int64_t *K, int eq, const double *params, int prec);
+Layout layout_for(int dim, int N, const int64_t *K, int eq, int prec);
+// Host-side description of a solve (mesh, operator, tiles, default launch
+// configuration); no device call.
+int setup_solver(dg_solver *h, int dim, int N, const int64_t *K, int equation, const double *params,
+                 int precision);
+// Point the table fields of h into device memory at p; returns the first
+// byte after the tables (the start of the state arrays).
+char *carve_tables(dg_solver *h, char *p);
+// Point A, Ya, Yb (and the RK6 store when rk6) at consecutive state-sized
+// arrays from p; returns the first byte after them.
+char *carve_rk_arrays(dg_solver *h, char *p, bool rk6);
+// Upload D, w and the face-point table to h's table fields on h's stream,
+// and wait for them.
+int upload_tables(dg_solver *h);
+// Enqueue nsteps steps of scheme rk on h's stream (arguments already checked,
+// device selected, RK6 storage in place).
+int enqueue_steps(dg_solver *h, int rk, double dt, int64_t nsteps);
 // Launch parameters common to every stage of h (mesh, operator, tiles).
 StageParams base_params(const dg_solver *h);
 // Number of fused stages of scheme rk (3, 4 or 7 for RK6).

@@ -58,7 +58,9 @@ SIGNATURES = {
     "dg_batch_size": (_I, [_P, _P, _P]),
     "dg_batch_synchronize": (_I, [_P]),
     "dg_bandwidth_probe": (_I, [_P, _P, _I, _P, _I, _I64]),
+    "dg_step_static": (_I, [_I, _I, _P, _I, _P, _I, _P, _P, _I64, _I, _D, _I64]),
 }
+DG_STATIC_SCRATCH_BYTES = 128 << 20
 DG_BATCH_GRAPH = 1
 
 _lib = None
@@ -266,6 +268,26 @@ def dg_bandwidth_probe(hip_stream, ins, outs, nbytes):
     oa = (ctypes.c_void_p * len(outs))(*[_dev_ptr_any(x).value for x in outs])
     _call("dg_bandwidth_probe", ctypes.c_void_p(hip_stream) if hip_stream else None, ia, len(ins), oa,
           len(outs), int(nbytes))
+
+
+def dg_step_static(dim, N, K, equation, params, precision, hip_stream, u_dev, rk, dt, nsteps,
+                   count=None):
+    """Step a device state in place with no device allocation (work memory
+    from the library's static scratch). u_dev: a contiguous CUDA tensor of
+    the state precision (float64 for DG_FP64, float32 for DG_FP32) or an
+    integer address with `count`."""
+    if hasattr(u_dev, "data_ptr"):
+        import torch
+        want = torch.float64 if precision == DG_FP64 else torch.float32
+        if u_dev.dtype != want or not u_dev.is_cuda or not u_dev.is_contiguous():
+            raise ValueError(f"u_dev must be a contiguous {want} tensor on the GPU")
+        count = u_dev.numel() if count is None else count
+        ptr = ctypes.c_void_p(u_dev.data_ptr())
+    else:
+        ptr = ctypes.c_void_p(int(u_dev)) if u_dev else None
+    _call("dg_step_static", int(dim), int(N), _ptr(_K(dim, K)), int(equation), _ptr(_params(params)),
+          int(precision), ctypes.c_void_p(hip_stream) if hip_stream else None, ptr,
+          int(count if count is not None else 0), int(rk), float(dt), int(nsteps))
 
 
 def dg_last_error() -> str:

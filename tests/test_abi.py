@@ -130,3 +130,35 @@ def test_single_hip_runtime_in_process():
     hip = set(re.findall(r"\S*libamdhip64\S*", maps))
     hsa = set(re.findall(r"\S*libhsa-runtime64\S*", maps))
     assert len(hip) == 1 and len(hsa) == 1, (hip, hsa)
+
+
+def test_step_static_validates_before_touching_a_device():
+    """dg_step_static's argument and size checks need no GPU."""
+    lib = dg.load()
+    K = np.array([16, 16], dtype=np.int64)
+    p = np.array([1.0, 0.5])
+    kp, pp = K.ctypes.data_as(ctypes.c_void_p), p.ctypes.data_as(ctypes.c_void_p)
+    n = 16 * 16 * 16
+    fake = ctypes.c_void_p(1 << 20)          # never dereferenced: every call below fails a check
+    assert lib.dg_step_static(4, 3, kp, 0, pp, 0, None, fake, n, 4, 0.1, 1) == dg.DG_EINVAL
+    assert lib.dg_step_static(2, 3, kp, 0, pp, 0, None, None, n, 4, 0.1, 1) == dg.DG_EINVAL
+    assert lib.dg_step_static(2, 3, kp, 0, pp, 0, None, fake, n + 1, 4, 0.1, 1) == dg.DG_EINVAL
+    assert lib.dg_step_static(2, 3, kp, 0, pp, 0, None, fake, n, 5, 0.1, 1) == dg.DG_EINVAL
+    assert lib.dg_step_static(2, 3, kp, 0, pp, 0, None, fake, n, 4, -0.1, 1) == dg.DG_EINVAL
+    assert lib.dg_step_static(2, 3, kp, 0, pp, 0, None, fake, n, 4, 0.1, -1) == dg.DG_EINVAL
+    assert lib.dg_step_static(2, 3, kp, 0, pp, 2, None, fake, n, 4, 0.1, 1) == dg.DG_EINVAL
+    odd = ctypes.c_void_p((1 << 20) + 4)
+    assert lib.dg_step_static(2, 3, kp, 0, pp, 0, None, odd, n, 4, 0.1, 1) == dg.DG_EINVAL
+    # larger than the static scratch: 3 RK work arrays of 2-D 512^2 N = 7 FP64
+    Kb = np.array([512, 512], dtype=np.int64)
+    nb = 512 * 512 * 64
+    assert 3 * nb * 8 > dg.DG_STATIC_SCRATCH_BYTES
+    rc = lib.dg_step_static(2, 7, Kb.ctypes.data_as(ctypes.c_void_p), 0, pp, 0, None, fake, nb, 4, 0.1, 1)
+    assert rc == dg.DG_ENOMEM
+    assert "static scratch" in dg.dg_last_error()
+    # the RK6 limit is lower (8 work arrays): a mesh that fits RK4 but not RK6
+    Km = np.array([256, 256], dtype=np.int64)
+    nm = 256 * 256 * 64
+    assert 3 * nm * 8 < dg.DG_STATIC_SCRATCH_BYTES < 8 * nm * 8
+    rc = lib.dg_step_static(2, 7, Km.ctypes.data_as(ctypes.c_void_p), 0, pp, 0, None, fake, nm, 6, 0.1, 1)
+    assert rc == dg.DG_ENOMEM
