@@ -95,7 +95,7 @@ def load_traffic(workload: str, precision: str, rk: int, launch_cfg):
     if rec.get("rk") != rk:
         return None
     cfg = rec.get("launch_config")
-    if cfg is not None and list(cfg) != [launch_cfg[0], launch_cfg[1], launch_cfg[4]]:
+    if cfg is not None and list(cfg) != [launch_cfg[0], launch_cfg[1], launch_cfg[4], launch_cfg[5]]:
         return None
     return rec.get("bytes_per_launch")
 
@@ -277,8 +277,9 @@ def main():
     ap.add_argument("--chunk", type=int, default=32)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--efficiency", action="store_true", help="error vs computing time study")
-    ap.add_argument("--launch-config", default=None, metavar="ORDER,SLAB,XBLOCK",
-                    help="tile order (0 XCD-contiguous, 1 plain), z-slab, x-block to time")
+    ap.add_argument("--launch-config", default=None, metavar="ORDER,SLAB,XBLOCK[,ZLEN]",
+                    help="tile order (0 XCD-contiguous, 1 plain), z-slab, x-block and z-march "
+                         "length (layers per workgroup) to time")
     ap.add_argument("--autotune", action="store_true",
                     help="autotune the launch configuration before timing (the committed traffic "
                          "counters are for the default configuration)")
@@ -329,7 +330,7 @@ def main():
         "timing": head["timing"],
         "launch_config": {"tile_order": "plain" if lc[0] else "xcd_contiguous",
                           "z_slab": lc[1], "halo_divisor_1d": lc[2],
-                          "x_block": lc[4], "autotuned": bool(lc[3])},
+                          "x_block": lc[4], "z_march": lc[5], "autotuned": bool(lc[3])},
         "nodes_per_s": head["nodes_per_s"],
         "copy_gbps": copy_gbs,
         "mass_drift": head["mass_drift"],
@@ -375,9 +376,11 @@ def measure(w, prec, rk, steps, warmup, repeats, stream, launch_config=None, aut
     s.set_state(U0)
     m0 = s.mass()
     if launch_config:
-        order, slab, xblk = (int(x) for x in launch_config.split(","))
+        vals = [int(x) for x in launch_config.split(",")]
         c = list(s.launch_config())
-        c[0], c[1], c[4] = order, slab, xblk
+        c[0], c[1], c[4] = vals[:3]
+        if len(vals) > 3:
+            c[5] = vals[3]
         s.set_launch_config(c)
     lc = s.autotune(rk, dt, 3) if autotune else s.launch_config()
     s.step(rk, dt, warmup)

@@ -214,25 +214,30 @@ void *dg_stream(const dg_solver *h);
  * tile order (XCD-contiguous or plain) x the z-slab size x the x-block
  * width; 2-D, the tile order; 1-D RK3/RK4 meshes split into chunks, the
  * steps per launch (via the halo bound). Every candidate computes the same
- * results bit for bit; only speed differs. Synchronous. Needs a
- * library-owned workspace (DG_ENOTSUP otherwise: it allocates one
- * state-sized copy); DG_ESTATE before the first set_state or for a batch
- * member. */
+ * results bit for bit; only speed differs. Synchronous. The tuner keeps
+ * one copy of the state: a library-owned workspace allocates it; an external
+ * workspace must hold it after the scheme's arrays, i.e. be at least
+ * dg_workspace_bytes(rk) plus one state array (nvar * nodes values of the
+ * state precision, rounded up to 256 bytes), DG_ENOTSUP otherwise.
+ * DG_ESTATE before the first set_state or for a batch member. */
 int dg_autotune(dg_solver *h, int rk, double dt, int trial_steps);
 
 /* The launch configuration in use: cfg[0] tile order (0 XCD-contiguous,
- * 1 plain), cfg[1] z-slab size (z-layers visited together), cfg[2] 1-D
+ * 1 plain), cfg[1] z-slab size (z-units visited together), cfg[2] 1-D
  * halo-bound divisor (steps per launch = capacity / (cfg[2] * stages)),
  * cfg[3] 1 once autotuned, cfg[4] x-block width (x-tiles visited together;
- * the number of x-tiles by default). Writes min(n, 5) entries and zeros
- * beyond. */
+ * the number of x-tiles by default), cfg[5] z-march length (3-D RK3/RK4: a
+ * workgroup runs cfg[5] consecutive layers of one tile column bottom to top
+ * and takes each lower z-face's other side from the layer it ran before;
+ * 1 = one layer per workgroup). Writes min(n, 6) entries and zeros beyond. */
 int dg_launch_config(const dg_solver *h, int64_t *cfg, int n);
 
-/* Set the launch configuration (same layout as dg_launch_config, n = 5;
+/* Set the launch configuration (same layout as dg_launch_config, n = 6;
  * cfg[3] is ignored and the autotuned flag cleared), e.g. to reapply a
- * configuration found by dg_autotune in an earlier run. 3-D: cfg[1] must
- * divide K[2] and cfg[4] the number of x-tiles; 1-D/2-D: cfg[1] and cfg[4]
- * must equal the values in use. cfg[0] in {0, 1}, cfg[2] in 1..1024. Every
+ * configuration found by dg_autotune in an earlier run. 3-D: cfg[5] in
+ * 1..K[2], cfg[1] must divide the number of z-units ceil(K[2] / cfg[5]) and
+ * cfg[4] the number of x-tiles; 1-D/2-D: cfg[1], cfg[4] and cfg[5] must
+ * equal the values in use. cfg[0] in {0, 1}, cfg[2] in 1..1024. Every
  * configuration computes the same results bit for bit. DG_EINVAL on a bad
  * entry (nothing changed), DG_ESTATE for a batch member. Takes effect at the
  * next dg_step; work already enqueued is unaffected. */
@@ -311,15 +316,16 @@ int dg_batch_synchronize(dg_batch *b);
  *                canonical layout, aligned to its element size; advanced in
  *                place. Owned by the caller.
  *   rk, dt, nsteps   as dg_step (DG_RK3, DG_RK4, DG_RK6; nsteps 0 is a no-op)
- * Work memory: the operator tables and the Runge-Kutta work arrays (3 state
- * arrays for RK3/RK4, 8 for RK6) come from the library's fixed device array
+ * Work memory: the operator tables, the Runge-Kutta work arrays (3 state
+ * arrays for RK3/RK4, 8 for RK6) and, for isothermal Euler, the device-layout
+ * copy of the state (1 more array) come from the library's fixed device array
  * of DG_STATIC_SCRATCH_BYTES bytes on the current device. A problem needing
  * more gives DG_ENOMEM, with the bytes needed in dg_last_error() (limit for
- * RK4: about DG_STATIC_SCRATCH_BYTES / 3 bytes per state array, e.g. 2-D
- * advection 256^2 N = 7 in FP64).
- * Asynchronous like dg_step, except that a call whose (dim, N, precision)
- * differs from the previous call's on the same device uploads the operator
- * tables and waits for hip_stream. Results are bitwise those of a solver made
+ * RK4 advection: about DG_STATIC_SCRATCH_BYTES / 3 bytes per state array,
+ * e.g. 2-D advection 256^2 N = 7 in FP64).
+ * Asynchronous like dg_step, except that a call whose (dim, N, equation,
+ * precision) differs from the previous call's on the same device uploads the
+ * operator tables and waits for hip_stream. Results are bitwise those of a solver made
  * with dg_create_ex on the same arguments, given the same state and stepped
  * with dg_step.
  * Every call on one GPU shares that GPU's array and leaves its contents

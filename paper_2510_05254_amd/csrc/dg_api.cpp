@@ -101,7 +101,9 @@ int select_device(const dg_solver *h)
     return DG_OK;
 }
 
-StageParams base_params(const dg_solver *h)
+int64_t z_units(const dg_solver *h) { return (h->K[2] + h->zlen - 1) / h->zlen; }
+
+StageParams base_params(const dg_solver *h, bool zmarch)
 {
     StageParams p;
     std::memset(&p, 0, sizeof(p));
@@ -114,17 +116,25 @@ StageParams base_params(const dg_solver *h)
     p.D = h->Dtab;
     p.tiles_x = h->tiles_x;
     p.tiles_y = h->tiles_y;
-    p.slab = h->slab;
+    // units along z: chunks of zlen layers for the z-marching kernel, layers
+    // otherwise (a z-slab that divides the chunk count but not K_z then
+    // falls back to 1 for the one-layer kernels)
+    const bool zm = zmarch && h->dim == 3 && h->zlen > 1;
+    const int64_t nz = zm ? z_units(h) : h->K[2];
+    const int64_t slab = nz % h->slab == 0 ? h->slab : 1;
+    const int64_t units = h->tiles_x * h->tiles_y * nz;
+    p.zlen = zm ? (uint32_t)h->zlen : 1u;
+    p.slab = slab;
     p.xblk = h->xblk;
-    p.ntiles = h->ntiles;
-    p.ntiles32 = (uint32_t)h->ntiles;
-    p.xq = (uint32_t)(h->ntiles / kXcds);
-    p.xr = (uint32_t)(h->ntiles % kXcds);
+    p.ntiles = units;
+    p.ntiles32 = (uint32_t)units;
+    p.xq = (uint32_t)(units / kXcds);
+    p.xr = (uint32_t)(units % kXcds);
     p.fd_tx = make_fastdiv((uint32_t)h->tiles_x);
-    p.fd_slab = make_fastdiv((uint32_t)h->slab);
+    p.fd_slab = make_fastdiv((uint32_t)slab);
     p.fd_ty = make_fastdiv((uint32_t)h->tiles_y);
     p.fd_xb = make_fastdiv((uint32_t)h->xblk);
-    p.fd_nslab = make_fastdiv((uint32_t)(h->K[2] / h->slab));
+    p.fd_nslab = make_fastdiv((uint32_t)(nz / slab));
     p.ftab = h->ftab;
     p.plain_order = (uint32_t)h->plain_order;
     return p;
@@ -146,9 +156,9 @@ void set_out(StageParams &p, int o, void *ptr, double cy, double c0, double c1, 
 
 // Fused-stage programs of the RK3 and RK4 schedules (see the file comment):
 // stage s reads yin (and in0/in1), writes out0/out1 = cy yin + c0 in0 + c1 in1 + cr R.
-StageParams stage_program(const dg_solver *h, int rk, int s, double dt)
+StageParams stage_program(const dg_solver *h, int rk, int s, double dt, bool zmarch)
 {
-    StageParams p = base_params(h);
+    StageParams p = base_params(h, zmarch);
     if (rk == DG_RK4) {
         switch (s) {
         case 0:
@@ -349,7 +359,7 @@ int upload_tables(dg_solver *h)
     const size_t fbytes = 16 * (size_t)face_table_size(h->dim, h->N, h->epb, h->epy);
     if (fbytes > kFaceTableBytes) return fail(DG_ENOTSUP, "face table larger than reserved");
     uint32_t ftab[kFaceTableBytes / 4];
-    build_face_table(h->dim, h->N, h->epb, h->epy, ftab);
+    build_face_table(h->dim, h->N, h->epb, h->epy, h->nvar, ftab);
     hipError_t e;
     if ((e = hipMemcpyAsync(h->Dtab, dbuf, dbytes, hipMemcpyHostToDevice, h->stream)) != hipSuccess ||
         (e = hipMemcpyAsync(h->ftab, ftab, fbytes, hipMemcpyHostToDevice, h->stream)) != hipSuccess ||
@@ -360,11 +370,30 @@ int upload_tables(dg_solver *h)
     return DG_OK;
 }
 
+double *staging(dg_solver *h)
+{
+    // Ya and Yb are adjacent and together hold at least unknowns doubles
+    return static_cast<double *>(h->Ya);
+}
+
+int convert(dg_solver *h, const void *src, int src_prec, void *dst, int dst_prec, bool to_internal)
+{
+    LayoutParams c;
+    c.src = src;
+    c.dst = dst;
+    c.nodes = h->nodes;
+    c.nvar = h->nvar;
+    c.np = h->np;
+    c.to_internal = to_internal ? 1 : 0;
+    DG_HIP(launch_layout(dst_prec, src_prec, c, h->stream), "layout kernel launch");
+    return DG_OK;
+}
+
 namespace {
 
 int launch(dg_solver *h, const StageParams &p)
 {
-    DG_HIP(h->stage(p, h->grid, h->stream), "stage kernel launch");
+    DG_HIP(h->stage(p, std::min<int64_t>(p.ntiles, kMaxGrid), h->stream), "stage kernel launch");
     return DG_OK;
 }
 
@@ -392,7 +421,7 @@ int ensure_rk6(dg_solver *h)
 int step_rk34(dg_solver *h, int rk, double dt)
 {
     for (int st = 0; st < stage_count(rk); ++st) {
-        int rc = launch(h, stage_program(h, rk, st, dt));
+        int rc = launch(h, stage_program(h, rk, st, dt, true));
         if (rc) return rc;
     }
     return DG_OK;
@@ -735,15 +764,15 @@ int dg_set_state(dg_solver *h, const double *u, int64_t count)
     if (h->batch) return fail(DG_ESTATE, "solver belongs to a batch");
     int rc = check_count(h, count);
     if (rc || (rc = select_device(h))) return rc;
-    if (h->prec == DG_FP64) {
+    if (h->prec == DG_FP64 && h->nvar == 1) {
         DG_HIP(hipMemcpyAsync(h->U, u, sizeof(double) * count, hipMemcpyHostToDevice, h->stream),
                "hipMemcpyAsync");
     } else {
-        std::vector<float> tmp(count);
-        for (int64_t i = 0; i < count; ++i) tmp[i] = (float)u[i];
-        DG_HIP(hipMemcpyAsync(h->U, tmp.data(), sizeof(float) * count, hipMemcpyHostToDevice, h->stream),
+        // variable-major FP64 into the free RK arrays, then converted into U
+        double *stage = staging(h);
+        DG_HIP(hipMemcpyAsync(stage, u, sizeof(double) * count, hipMemcpyHostToDevice, h->stream),
                "hipMemcpyAsync");
-        DG_HIP(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+        if ((rc = convert(h, stage, DG_FP64, h->U, h->prec, true))) return rc;
     }
     DG_HIP(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
     h->has_state = true;
@@ -756,12 +785,11 @@ int dg_set_state_device(dg_solver *h, const void *u_dev, int64_t count)
     if (h->batch) return fail(DG_ESTATE, "solver belongs to a batch");
     int rc = check_count(h, count);
     if (rc || (rc = select_device(h))) return rc;
-    if (h->prec == DG_FP64) {
+    if (h->prec == DG_FP64 && h->nvar == 1) {
         DG_HIP(hipMemcpyAsync(h->U, u_dev, sizeof(double) * count, hipMemcpyDeviceToDevice, h->stream),
                "hipMemcpyAsync");
-    } else {
-        CastParams c{u_dev, h->U, count};
-        DG_HIP(launch_cast(DG_FP32, DG_FP64, c, h->stream), "cast kernel launch");
+    } else if ((rc = convert(h, u_dev, DG_FP64, h->U, h->prec, true))) {
+        return rc;
     }
     h->has_state = true;
     return DG_OK;
@@ -788,17 +816,15 @@ int dg_get_state(dg_solver *h, double *u, int64_t count)
     int rc = check_count(h, count);
     if (rc || (rc = select_device(h))) return rc;
     if (!h->has_state) return fail(DG_ESTATE, "dg_set_state has not been called");
-    if (h->prec == DG_FP64) {
-        DG_HIP(hipMemcpyAsync(u, h->U, sizeof(double) * count, hipMemcpyDeviceToHost, h->stream),
-               "hipMemcpyAsync");
-        DG_HIP(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
-    } else {
-        std::vector<float> tmp(count);
-        DG_HIP(hipMemcpyAsync(tmp.data(), h->U, sizeof(float) * count, hipMemcpyDeviceToHost, h->stream),
-               "hipMemcpyAsync");
-        DG_HIP(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
-        for (int64_t i = 0; i < count; ++i) u[i] = (double)tmp[i];
+    const void *src = h->U;
+    if (!(h->prec == DG_FP64 && h->nvar == 1)) {
+        // converted to variable-major FP64 in the free RK arrays first
+        double *stage = staging(h);
+        if ((rc = convert(h, h->U, h->prec, stage, DG_FP64, false))) return rc;
+        src = stage;
     }
+    DG_HIP(hipMemcpyAsync(u, src, sizeof(double) * count, hipMemcpyDeviceToHost, h->stream), "hipMemcpyAsync");
+    DG_HIP(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
     return DG_OK;
 }
 
@@ -808,12 +834,11 @@ int dg_get_state_device(dg_solver *h, void *u_dev, int64_t count)
     int rc = check_count(h, count);
     if (rc || (rc = select_device(h))) return rc;
     if (!h->has_state) return fail(DG_ESTATE, "dg_set_state has not been called");
-    if (h->prec == DG_FP64) {
+    if (h->prec == DG_FP64 && h->nvar == 1) {
         DG_HIP(hipMemcpyAsync(u_dev, h->U, sizeof(double) * count, hipMemcpyDeviceToDevice, h->stream),
                "hipMemcpyAsync");
-    } else {
-        CastParams c{h->U, u_dev, count};
-        DG_HIP(launch_cast(DG_FP64, DG_FP32, c, h->stream), "cast kernel launch");
+    } else if ((rc = convert(h, h->U, h->prec, u_dev, DG_FP64, false))) {
+        return rc;
     }
     return DG_OK;
 }
@@ -871,80 +896,118 @@ int dg_autotune(dg_solver *h, int rk, double dt, int trial_steps)
     if (trial_steps < 1 || trial_steps > 1000) return fail(DG_EINVAL, "trial_steps must be in 1..1000");
     if (!h->has_state) return fail(DG_ESTATE, "dg_set_state has not been called");
     if (h->batch) return fail(DG_ESTATE, "solver belongs to a batch");
-    if (!h->own_ws) return fail(DG_ENOTSUP, "autotuning needs a library-owned workspace");
+    // the tuner keeps a copy of the state: its own allocation for a
+    // library-owned workspace, else the space after the scheme's arrays in
+    // the caller's workspace
+    const size_t used = rk == DG_RK6 ? h->lay.rk6 : h->lay.base;
+    if (!h->own_ws && h->ws_bytes < used + h->lay.array)
+        return fail(DG_ENOTSUP, "autotuning with an external workspace needs one state array more than "
+                                "dg_workspace_bytes(rk) for its copy of the state");
     int rc = select_device(h);
     if (rc) return rc;
     if (rk == DG_RK6 && (rc = ensure_rk6(h))) return rc;
 
-    // candidate launch configurations (tile order, z-slab, x-block, 1-D halo bound)
-    struct Cfg { int plain, ms_div; int64_t slab, xblk; };
-    std::vector<Cfg> cand;
-    const bool ms = ms_plan(h, rk).ok;
-    if (ms) {
-        if (!ms_plan(h, rk).whole)
-            for (int dv : {3, 4, 6, 10, 16}) cand.push_back({h->plain_order, dv, h->slab, h->xblk});
+    // Launch configurations (tile order, 1-D halo bound, z-slab, x-block,
+    // z-march length), searched in stages: 3-D, first tile order x x-block
+    // (one-layer units), then the z-slab, then the z-march length (RK3/RK4
+    // only: the RK6 kernel runs one layer per tile); 2-D, the tile order;
+    // 1-D chunked meshes, the halo bound. Each stage keeps the fastest of its
+    // candidates and the incumbent. Every candidate is timed for trial_steps
+    // steps from a saved copy of U (after one warm-up step), then U is
+    // restored.
+    struct Cfg { int plain, ms_div; int64_t slab, xblk, zlen; };
+    const Cfg keep = {h->plain_order, h->ms_div, h->slab, h->xblk, h->zlen};
+    std::vector<std::vector<Cfg>> stages;
+    const MsPlan pl = ms_plan(h, rk);
+    if (pl.ok) {
+        if (!pl.whole) {
+            std::vector<Cfg> st;
+            for (int dv : {3, 4, 6, 10, 16}) st.push_back({h->plain_order, dv, h->slab, h->xblk, h->zlen});
+            stages.push_back(st);
+        }
     } else if (h->dim == 3) {
-        // x-blocks: the whole row, then halvings down to 2 tiles
-        std::vector<int64_t> xbs{h->tiles_x};
+        std::vector<int64_t> xbs{h->tiles_x};          // the whole row, then halvings down to 2 tiles
         for (int64_t xb = h->tiles_x; xb % 2 == 0 && xb / 2 >= 2; xb /= 2) xbs.push_back(xb / 2);
+        std::vector<Cfg> s1;
         for (int plain = 0; plain <= 1; ++plain)
-            for (int64_t sl = 1; sl <= h->K[2]; sl *= 2)
-                if (h->K[2] % sl == 0)
-                    for (int64_t xb : xbs) cand.push_back({plain, h->ms_div, sl, xb});
-    } else {
-        for (int plain = 0; plain <= 1; ++plain) cand.push_back({plain, h->ms_div, h->slab, h->xblk});
+            for (int64_t xb : xbs) s1.push_back({plain, h->ms_div, 1, xb, 1});
+        stages.push_back(s1);
+        stages.push_back({});                          // z-slabs: filled from the stage-1 winner
+        if (rk != DG_RK6) stages.push_back({});        // z-march lengths: filled likewise
+    } else if (h->dim == 2) {
+        stages.push_back({{0, h->ms_div, h->slab, h->xblk, h->zlen}, {1, h->ms_div, h->slab, h->xblk, h->zlen}});
     }
-    if (cand.size() < 2) {
+    if (stages.empty()) {
         h->tuned = 1;
         return DG_OK;
     }
-    // time each candidate on the solver's own arrays from a saved copy of U,
-    // then restore U
     void *save = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipError_t e = hipMalloc(&save, h->lay.array);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(DG_ENOMEM, "cannot allocate the autotuning copy of the state");
+    hipError_t e = hipSuccess;
+    if (h->own_ws) {
+        e = hipMalloc(&save, h->lay.array);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(DG_ENOMEM, "cannot allocate the autotuning copy of the state");
+        }
+    } else {
+        save = h->ws + used;
     }
     rc = DG_OK;
-    Cfg best = cand[0];
-    float best_ms = -1.0f;
-    const Cfg keep = {h->plain_order, h->ms_div, h->slab, h->xblk};
+    auto apply = [h](const Cfg &c) {
+        h->plain_order = c.plain;
+        h->ms_div = c.ms_div;
+        h->slab = c.slab;
+        h->xblk = c.xblk;
+        h->zlen = c.zlen;
+    };
+    // time one candidate; U is restored afterwards
+    auto time_cfg = [&](const Cfg &c, float &ms_t) {
+        apply(c);
+        rc = dg_step(h, rk, dt, 1);                                   // warm-up
+        if (rc) return;
+        e = hipMemcpyAsync(h->U, save, h->lay.array, hipMemcpyDeviceToDevice, h->stream);
+        if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
+        if (e != hipSuccess) return;
+        rc = dg_step(h, rk, dt, trial_steps);
+        if (rc) return;
+        e = hipEventRecord(e1, h->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms_t, e0, e1);
+        if (e == hipSuccess) e = hipMemcpyAsync(h->U, save, h->lay.array, hipMemcpyDeviceToDevice, h->stream);
+    };
     e = hipMemcpyAsync(save, h->U, h->lay.array, hipMemcpyDeviceToDevice, h->stream);
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
-    for (size_t i = 0; e == hipSuccess && rc == DG_OK && i < cand.size(); ++i) {
-        h->plain_order = cand[i].plain;
-        h->ms_div = cand[i].ms_div;
-        h->slab = cand[i].slab;
-        h->xblk = cand[i].xblk;
-        rc = dg_step(h, rk, dt, 1);                                   // warm-up
-        if (rc) break;
-        e = hipMemcpyAsync(h->U, save, h->lay.array, hipMemcpyDeviceToDevice, h->stream);
-        if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
-        if (e != hipSuccess) break;
-        rc = dg_step(h, rk, dt, trial_steps);
-        if (rc) break;
-        e = hipEventRecord(e1, h->stream);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms_t = 0.0f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms_t, e0, e1);
-        if (e == hipSuccess && (best_ms < 0.0f || ms_t < best_ms)) {
-            best_ms = ms_t;
-            best = cand[i];
+    Cfg best = keep;
+    float best_ms = -1.0f;
+    for (size_t si = 0; si < stages.size() && e == hipSuccess && rc == DG_OK; ++si) {
+        std::vector<Cfg> cand = stages[si];
+        if (h->dim == 3 && !pl.ok && si == 1) {
+            for (int64_t sl = 2; sl <= h->K[2]; sl *= 2)
+                if (h->K[2] % sl == 0) cand.push_back({best.plain, best.ms_div, sl, best.xblk, 1});
+        } else if (h->dim == 3 && !pl.ok && si == 2) {
+            for (int64_t zl : {2, 4, 8, 16}) {
+                if (zl > h->K[2]) break;
+                const int64_t nz = (h->K[2] + zl - 1) / zl;
+                cand.push_back({best.plain, best.ms_div, nz % best.slab == 0 ? best.slab : 1, best.xblk, zl});
+            }
         }
-        if (e == hipSuccess) e = hipMemcpyAsync(h->U, save, h->lay.array, hipMemcpyDeviceToDevice, h->stream);
+        for (const Cfg &c : cand) {
+            float ms_t = 0.0f;
+            time_cfg(c, ms_t);
+            if (e != hipSuccess || rc != DG_OK) break;
+            if (best_ms < 0.0f || ms_t < best_ms) {
+                best_ms = ms_t;
+                best = c;
+            }
+        }
     }
     if (e == hipSuccess && rc == DG_OK) e = hipStreamSynchronize(h->stream);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    (void)hipFree(save);
-    const Cfg use = (e == hipSuccess && rc == DG_OK) ? best : keep;
-    h->plain_order = use.plain;
-    h->ms_div = use.ms_div;
-    h->slab = use.slab;
-    h->xblk = use.xblk;
+    if (h->own_ws) (void)hipFree(save);
+    apply((e == hipSuccess && rc == DG_OK) ? best : keep);
     if (rc) return rc;
     if (e != hipSuccess) return hip_fail(e, "autotuning");
     h->tuned = 1;
@@ -954,7 +1017,7 @@ int dg_autotune(dg_solver *h, int rk, double dt, int trial_steps)
 int dg_launch_config(const dg_solver *h, int64_t *cfg, int n)
 {
     if (!h || !cfg || n < 0) return fail(DG_EINVAL, "NULL argument or n < 0");
-    const int64_t v[kLaunchCfg] = {h->plain_order, h->slab, h->ms_div, h->tuned, h->xblk};
+    const int64_t v[kLaunchCfg] = {h->plain_order, h->slab, h->ms_div, h->tuned, h->xblk, h->zlen};
     for (int i = 0; i < n && i < kLaunchCfg; ++i) cfg[i] = v[i];
     for (int i = kLaunchCfg; i < n; ++i) cfg[i] = 0;
     return DG_OK;
@@ -963,22 +1026,27 @@ int dg_launch_config(const dg_solver *h, int64_t *cfg, int n)
 int dg_set_launch_config(dg_solver *h, const int64_t *cfg, int n)
 {
     if (!h || !cfg) return fail(DG_EINVAL, "NULL argument");
-    if (n != kLaunchCfg) return fail(DG_EINVAL, "n must be 5");
+    if (n != kLaunchCfg) return fail(DG_EINVAL, "n must be 6");
     if (h->batch) return fail(DG_ESTATE, "solver belongs to a batch");
-    const int64_t plain = cfg[0], slab = cfg[1], ms_div = cfg[2], xblk = cfg[4];
+    const int64_t plain = cfg[0], slab = cfg[1], ms_div = cfg[2], xblk = cfg[4], zlen = cfg[5];
     if (plain != 0 && plain != 1) return fail(DG_EINVAL, "cfg[0] (tile order) must be 0 or 1");
     if (ms_div < 1 || ms_div > 1024) return fail(DG_EINVAL, "cfg[2] (halo-bound divisor) must be in 1..1024");
     if (h->dim == 3) {
-        if (slab < 1 || h->K[2] % slab != 0) return fail(DG_EINVAL, "cfg[1] (z-slab) must divide K[2]");
+        if (zlen < 1 || zlen > h->K[2]) return fail(DG_EINVAL, "cfg[5] (z-march length) must be in 1..K[2]");
+        const int64_t nz = (h->K[2] + zlen - 1) / zlen;
+        if (slab < 1 || nz % slab != 0)
+            return fail(DG_EINVAL, "cfg[1] (z-slab) must divide the number of z-units ceil(K[2] / cfg[5])");
         if (xblk < 1 || h->tiles_x % xblk != 0)
             return fail(DG_EINVAL, "cfg[4] (x-block) must divide the number of x-tiles");
-    } else if (slab != h->slab || xblk != h->xblk) {
-        return fail(DG_EINVAL, "z-slab and x-block apply to 3-D meshes only (pass the values in use)");
+    } else if (slab != h->slab || xblk != h->xblk || zlen != h->zlen) {
+        return fail(DG_EINVAL, "z-slab, x-block and z-march length apply to 3-D meshes only "
+                               "(pass the values in use)");
     }
     h->plain_order = (int)plain;
     h->slab = slab;
     h->ms_div = (int)ms_div;
     h->xblk = xblk;
+    h->zlen = zlen;
     h->tuned = 0;
     return DG_OK;
 }

@@ -68,7 +68,15 @@ struct dg_batch {
     bool dirty = true;
     char *dbuf = nullptr;
     size_t dbuf_cap = 0;
-    std::vector<char> staging;
+    // descriptors are staged in pinned host memory, two slots used in turn:
+    // a slot is rewritten once the copy out of it (stream-ordered behind the
+    // ticks enqueued before it) has run, so a rebuild never waits for the
+    // whole stream
+    char *pin[2] = {nullptr, nullptr};
+    size_t pin_cap[2] = {0, 0};
+    hipEvent_t pin_ev[2] = {nullptr, nullptr};
+    bool pin_used[2] = {false, false};
+    int pin_slot = 0;
     hipEvent_t done = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -159,11 +167,27 @@ int rebuild(dg_batch *b)
         g.off_solve = total;
         total = round_up(total + sizeof(uint32_t) * g.ntiles);
     }
-    b->staging.resize(header);
+    // the staging slot: wait for the copy that last read it, grow it if needed
+    const int slot = b->pin_slot;
+    if (b->pin_used[slot]) DG_HIP(hipEventSynchronize(b->pin_ev[slot]), "hipEventSynchronize");
+    if (header > b->pin_cap[slot]) {
+        const size_t cap = std::max(header, 2 * b->pin_cap[slot]);     // grow geometrically
+        if (b->pin[slot]) (void)hipHostFree(b->pin[slot]);
+        b->pin[slot] = nullptr;
+        b->pin_cap[slot] = 0;
+        hipError_t e = hipHostMalloc((void **)&b->pin[slot], cap, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            b->pin[slot] = nullptr;
+            return fail(DG_ENOMEM, "cannot allocate pinned batch staging");
+        }
+        b->pin_cap[slot] = cap;
+    }
+    char *staging = b->pin[slot];
     for (Group &g : b->groups) {
         const size_t n = g.idx.size();
-        StageParams *par = reinterpret_cast<StageParams *>(b->staging.data() + g.off_params);
-        uint32_t *base = reinterpret_cast<uint32_t *>(b->staging.data() + g.off_base);
+        StageParams *par = reinterpret_cast<StageParams *>(staging + g.off_params);
+        uint32_t *base = reinterpret_cast<uint32_t *>(staging + g.off_base);
         uint32_t t0 = 0;
         for (size_t j = 0; j < n; ++j) {
             const Member &m = b->members[g.idx[j]];
@@ -193,15 +217,18 @@ int rebuild(dg_batch *b)
         }
         b->dbuf_cap = total;
     }
-    DG_HIP(hipMemcpyAsync(b->dbuf, b->staging.data(), header, hipMemcpyHostToDevice, b->stream),
-           "hipMemcpyAsync");
+    // stream-ordered after the ticks already enqueued, which still read the
+    // previous descriptors
+    DG_HIP(hipMemcpyAsync(b->dbuf, staging, header, hipMemcpyHostToDevice, b->stream), "hipMemcpyAsync");
+    if (!b->pin_ev[slot]) DG_HIP(hipEventCreateWithFlags(&b->pin_ev[slot], hipEventDisableTiming), "hipEventCreate");
+    DG_HIP(hipEventRecord(b->pin_ev[slot], b->stream), "hipEventRecord");
+    b->pin_used[slot] = true;
+    b->pin_slot = slot ^ 1;
     for (const Group &g : b->groups)
         DG_HIP(launch_fill_tile_map(reinterpret_cast<const uint32_t *>(b->dbuf + g.off_base),
                                     (uint32_t)g.idx.size(),
                                     reinterpret_cast<uint32_t *>(b->dbuf + g.off_solve), b->stream),
                "tile map launch");
-    // the staging buffer is reused by the next rebuild
-    DG_HIP(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
     return DG_OK;
 }
 
@@ -281,6 +308,10 @@ int dg_batch_destroy(dg_batch *b)
     for (Member &m : b->members) m.h->batch = nullptr;
     drop_graph(b);
     if (b->dbuf) (void)hipFree(b->dbuf);
+    for (int i = 0; i < 2; ++i) {
+        if (b->pin[i]) (void)hipHostFree(b->pin[i]);
+        if (b->pin_ev[i]) (void)hipEventDestroy(b->pin_ev[i]);
+    }
     if (b->done) (void)hipEventDestroy(b->done);
     if (b->own_stream) (void)hipStreamDestroy(b->stream);
     delete b;

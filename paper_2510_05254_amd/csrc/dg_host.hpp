@@ -20,7 +20,8 @@ void lgl_operator(int N, double *xi, double *w, double *D);
 
 // Face-point descriptor table of a workgroup tile (4 uint32 per face point).
 int face_table_size(int dim, int N, int epb, int epy);
-void build_face_table(int dim, int N, int epb, int epy, uint32_t *tab);
+// nv: variables (values per element in the state arrays = nv * (N+1)^dim).
+void build_face_table(int dim, int N, int epb, int epy, int nv, uint32_t *tab);
 
 // Device workspace of one solver: tables, then the RK arrays.
 struct Layout {
@@ -44,7 +45,7 @@ size_t round_up(size_t x);
 }  // namespace dg
 
 // entries of a launch configuration (dg_launch_config / dg_set_launch_config)
-constexpr int kLaunchCfg = 5;
+constexpr int kLaunchCfg = 6;
 
 struct dg_solver {
     int dim = 0, N = 0, eq = 0, prec = 0, nvar = 0, n1 = 0, np = 0;
@@ -75,6 +76,7 @@ struct dg_solver {
     // follow from the halo bound capacity / (ms_div * stages)
     int plain_order = 0;
     int ms_div = 6;
+    int64_t zlen = 1;               // 3-D: layers per z-marching unit (1 = one layer per tile)
     int tuned = 0;
     dg_batch *batch = nullptr;      // batch this solver belongs to, if any
 };
@@ -98,15 +100,24 @@ char *carve_rk_arrays(dg_solver *h, char *p, bool rk6);
 // Upload D, w and the face-point table to h's table fields on h's stream,
 // and wait for them.
 int upload_tables(dg_solver *h);
+// Device staging area of at least unknowns doubles (the RK arrays Ya, Yb,
+// free between steps).
+double *staging(dg_solver *h);
+// Convert a state array between the ABI's variable-major layout and the
+// device's element-interleaved layout (to_internal: src variable-major), with
+// precisions src_prec -> dst_prec, on h's stream.
+int convert(dg_solver *h, const void *src, int src_prec, void *dst, int dst_prec, bool to_internal);
 // Enqueue nsteps steps of scheme rk on h's stream (arguments already checked,
 // device selected, RK6 storage in place).
 int enqueue_steps(dg_solver *h, int rk, double dt, int64_t nsteps);
 // Launch parameters common to every stage of h (mesh, operator, tiles).
-StageParams base_params(const dg_solver *h);
+// zmarch: for the single-solve RK3/RK4 stage kernel, whose 3-D classes run
+// units of h->zlen layers; otherwise one layer per tile.
+StageParams base_params(const dg_solver *h, bool zmarch = false);
 // Number of fused stages of scheme rk (3, 4 or 7 for RK6).
 int stage_count(int rk);
 // Parameters of fused stage s of the RK3/RK4 schedule with step dt.
-StageParams stage_program(const dg_solver *h, int rk, int s, double dt);
+StageParams stage_program(const dg_solver *h, int rk, int s, double dt, bool zmarch = false);
 
 // 1-D multi-step plan: whole mode (one workgroup holds the periodic mesh,
 // up to kMsWholeSteps steps per launch) when the mesh fits in one

@@ -69,6 +69,8 @@ struct StageParams {
     // slab, y-tile, slab, x-block) in 3-D by the divisions below.
     uint32_t ntiles32, xq, xr;
     uint32_t plain_order;  // 1: tile L = virtual block (no XCD renumbering)
+    uint32_t zlen;         // 3-D z-marching kernels: layers per unit (the
+                           // decoded z is then a chunk index); 1 elsewhere
     FastDiv fd_tx, fd_slab, fd_ty, fd_xb, fd_nslab;
     const uint32_t *ftab;  // face-point descriptors of a tile (dg_tables.cpp)
 };
@@ -83,7 +85,8 @@ struct BatchLaunch {
     uint32_t ntiles, xq, xr, nsolves;
 };
 
-// Quadrature reductions: per-block FP64 partial sums of
+// Quadrature reductions (state element-interleaved, reference variable-major):
+// per-block FP64 partial sums of
 //   mode 0 (mass): sum q_n U_v
 //   mode 1 (L2):   sum q_n (U_v - Uref_v)^2  and  sum q_n Uref_v^2
 // with q_n = prod_d (dx_d/2) w_{n_d}.
@@ -97,11 +100,15 @@ struct ReduceParams {
     int nvar, n1, np, dim, mode;
 };
 
-// Precision conversion between the canonical FP64 layout and the state type.
-struct CastParams {
+// Conversion between the ABI's variable-major layout and the device's
+// element-interleaved layout (to_internal: variable-major src, interleaved
+// dst; otherwise the reverse), with the precisions of the launch.
+struct LayoutParams {
     const void *src;
     void *dst;
-    int64_t n;
+    int64_t nodes;         // nodes per variable
+    int nvar, np;          // variables; nodes per element
+    int to_internal;
 };
 
 // ---------------------------------------------------------------------------
@@ -167,7 +174,7 @@ int stage_epb(int dim, int N);
 int stage_epy(int dim, int N);
 
 hipError_t launch_reduce(int precision, const ReduceParams &p, int64_t blocks, hipStream_t s);
-hipError_t launch_cast(int to_precision, int from_precision, const CastParams &p, hipStream_t s);
+hipError_t launch_layout(int to_precision, int from_precision, const LayoutParams &p, hipStream_t s);
 // tile_solve[t] = j for tile_base[j] <= t < tile_base[j+1], j < nsolves
 // (tile_base holds nsolves + 1 entries, the last one the total tile count).
 hipError_t launch_fill_tile_map(const uint32_t *tile_base, uint32_t nsolves, uint32_t *tile_solve,

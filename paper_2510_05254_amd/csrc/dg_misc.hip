@@ -154,20 +154,38 @@ template <typename real>
 __global__ void __launch_bounds__(kReduceThreads) reduce_kernel(const ReduceParams p)
 {
     constexpr int T = kReduceThreads;
+    __shared__ double qn[kMaxNP1 * kMaxNP1 * kMaxNP1];
     __shared__ double red[2 * 4][T];
+    // quadrature weight of each node of an element, jac * prod_d w_{n_d}
+    // (products in the same order for every node, once per block)
+    for (int n = threadIdx.x; n < p.np; n += T) {
+        int m = n;
+        double q = p.jac;
+        for (int d = 0; d < p.dim; ++d) {
+            q *= p.w[m % p.n1];
+            m /= p.n1;
+        }
+        qn[n] = q;
+    }
+    __syncthreads();
     const real *u = static_cast<const real *>(p.u);
     double acc[2 * 4];
     for (int k = 0; k < 2 * 4; ++k) acc[k] = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)T + threadIdx.x; i < p.stride;
-         i += (int64_t)gridDim.x * T) {
-        int n = int(i % p.np);
-        double q = p.jac;
-        for (int d = 0; d < p.dim; ++d) {
-            q *= p.w[n % p.n1];
-            n /= p.n1;
-        }
+    // grid-stride over nodes; the node index within the element advances by
+    // the stride modulo np (one division per thread instead of one per node)
+    const int64_t G = (int64_t)gridDim.x * T;
+    int64_t i = blockIdx.x * (int64_t)T + threadIdx.x;
+    int n = int(i % p.np);
+    const int step = int(G % p.np);
+    for (; i < p.stride; i += G) {
+        const double q = qn[n];
+        // u: element-interleaved (element of node i, then variable, then
+        // node); uref: variable-major
+        const int64_t ui = (i - n) * p.nvar + n;
+        n += step;
+        if (n >= p.np) n -= p.np;
         for (int v = 0; v < p.nvar; ++v) {
-            const double x = double(u[v * p.stride + i]);
+            const double x = double(u[ui + (int64_t)v * p.np]);
             if (p.mode == 0) {
                 acc[v] += q * x;
             } else {
@@ -199,25 +217,47 @@ hipError_t launch_reduce(int precision, const ReduceParams &p, int64_t blocks, h
 }
 
 // ---------------------------------------------------------------------------
-// precision casts
+// Layout and precision conversion between the ABI's variable-major arrays
+// (v * nodes + e * np + n) and the element-interleaved device arrays
+// (e * nvar * np + v * np + n); one thread per destination value, so the
+// writes are coalesced. Off the stepping path (set/get state).
 // ---------------------------------------------------------------------------
 template <typename To, typename From>
-__global__ void __launch_bounds__(256) cast_kernel(const CastParams p)
+__global__ void __launch_bounds__(256) layout_kernel(const LayoutParams p)
 {
     const From *src = static_cast<const From *>(p.src);
     To *dst = static_cast<To *>(p.dst);
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < p.n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        dst[i] = To(src[i]);
+    const int64_t es = (int64_t)p.nvar * p.np, total = p.nodes * p.nvar;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < total;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        int64_t k = j;
+        if (p.nvar > 1) {
+            if (p.to_internal) {                       // j internal -> k variable-major
+                const int64_t e = j / es, r = j - e * es;
+                const int64_t v = r / p.np, n = r - v * p.np;
+                k = v * p.nodes + e * p.np + n;
+            } else {                                   // j variable-major -> k internal
+                const int64_t v = j / p.nodes, r = j - v * p.nodes;
+                const int64_t e = r / p.np, n = r - e * p.np;
+                k = e * es + v * p.np + n;
+            }
+        }
+        dst[j] = To(src[k]);
+    }
 }
 
-hipError_t launch_cast(int to_precision, int from_precision, const CastParams &p, hipStream_t s)
+hipError_t launch_layout(int to_precision, int from_precision, const LayoutParams &p, hipStream_t s)
 {
-    const int64_t g = grid_for(p.n, 256);
-    if (to_precision == 1 && from_precision == 0)
-        hipLaunchKernelGGL((cast_kernel<float, double>), dim3((unsigned)g), dim3(256), 0, s, p);
+    const int64_t g = grid_for(p.nodes * p.nvar, 256);
+    const dim3 G((unsigned)g), B(256);
+    if (to_precision == 0 && from_precision == 0)
+        hipLaunchKernelGGL((layout_kernel<double, double>), G, B, 0, s, p);
+    else if (to_precision == 1 && from_precision == 0)
+        hipLaunchKernelGGL((layout_kernel<float, double>), G, B, 0, s, p);
     else if (to_precision == 0 && from_precision == 1)
-        hipLaunchKernelGGL((cast_kernel<double, float>), dim3((unsigned)g), dim3(256), 0, s, p);
+        hipLaunchKernelGGL((layout_kernel<double, float>), G, B, 0, s, p);
+    else if (to_precision == 1 && from_precision == 1)
+        hipLaunchKernelGGL((layout_kernel<float, float>), G, B, 0, s, p);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -114,7 +114,6 @@ __global__ void __launch_bounds__((Geo1<real, N, EQ>::THREADS)) ms1_kernel(const
     const int town = int(whole ? K : (K - own0 < P->T ? K - own0 : P->T));
     const int L = town + 2 * H;                             // local elements
     const int64_t gfirst = own0 - H;                        // global element of local 0
-    const int64_t stride = K * N1;
     const real par = real(P->par), rdx2 = real(P->rdx2);
     const real sl = rdx2 * INVW0;
 
@@ -127,7 +126,7 @@ __global__ void __launch_bounds__((Geo1<real, N, EQ>::THREADS)) ms1_kernel(const
         if (ge < 0) ge += K;
         if (ge >= K) ge -= K;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) sA[0][v][le * S + i] = U[v * stride + ge * N1 + i];
+        for (int v = 0; v < NV; ++v) sA[0][v][le * S + i] = U[(ge * NV + v) * N1 + i];
     }
     __syncthreads();
 
@@ -234,7 +233,7 @@ __global__ void __launch_bounds__((Geo1<real, N, EQ>::THREADS)) ms1_kernel(const
         const int le = idx / N1, i = idx - le * N1;
         const int64_t ge = gfirst + le;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) U[v * stride + ge * N1 + i] = sA[0][v][le * S + i];
+        for (int v = 0; v < NV; ++v) U[(ge * NV + v) * N1 + i] = sA[0][v][le * S + i];
     }
 }
 

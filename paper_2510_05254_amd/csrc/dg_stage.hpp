@@ -34,6 +34,10 @@
 // and a fixed reciprocal sequence, so a face shared by two tiles gets the same
 // Fhat bits on both sides and the scheme conserves to roundoff.
 //
+// Layout of the state arrays on the device (element-interleaved): element e
+// holds its variables one after another, value (v, e, n) at e * NV * NP +
+// v * NP + n, so a tile's variables are one contiguous run per row of
+// elements (the ABI's variable-major layout is converted at set/get).
 // Addressing: when every state array fits the 32-bit buffer range, loads and
 // stores are raw buffer instructions with one 32-bit offset per node (the
 // variable offset rides in the scalar offset); otherwise 64-bit pointers.
@@ -201,11 +205,14 @@ struct Arr<real, true> {
     using idx_t = uint32_t;
     __amdgpu_buffer_rsrc_t r;
     uint32_t vbytes;   // bytes between variables
-    __device__ __forceinline__ Arr(const void *p, int64_t stride, int nvar)
+    // nodes: nodes per variable; vstride: values between the variables of a
+    // node (the element's node count in the element-interleaved layout)
+    __device__ __forceinline__ Arr(const void *p, int64_t nodes, int nvar, int vstride)
     {
-        vbytes = uint32_t(stride * (int64_t)sizeof(real));
+        vbytes = uint32_t(vstride * (int64_t)sizeof(real));
         r = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0,
-                                              (int)(uint32_t(nvar) * vbytes), 0x00020000);
+                                              (int)(uint32_t(nvar) * uint32_t(nodes) * uint32_t(sizeof(real))),
+                                              0x00020000);
     }
     // (last argument: the instruction's cache-policy bits, default policy)
     __device__ __forceinline__ real ld(int v, idx_t node) const
@@ -233,8 +240,8 @@ struct Arr<real, false> {
     using idx_t = int64_t;
     real *p;
     int64_t stride;
-    __device__ __forceinline__ Arr(const void *ptr, int64_t s, int)
-        : p(static_cast<real *>(const_cast<void *>(ptr))), stride(s) {}
+    __device__ __forceinline__ Arr(const void *ptr, int64_t, int, int vstride)
+        : p(static_cast<real *>(const_cast<void *>(ptr))), stride(vstride) {}
     __device__ __forceinline__ real ld(int v, idx_t node) const { return p[v * stride + node]; }
     __device__ __forceinline__ void st(int v, idx_t node, real x) const { p[v * stride + node] = x; }
 };
@@ -244,7 +251,7 @@ struct Arr<real, false> {
 // flops in the volume term) or the velocities m_k (1/rho) (VEL = true:
 // smaller, so that more workgroups share a CU; the tensor entries are rebuilt
 // from them with the same operations, so the results are the same bits).
-template <typename real, int DIM, int N, int EQ, int TM, bool VEL>
+template <typename real, int DIM, int N, int EQ, int TM, bool VEL, bool ZM = false>
 struct StageLds {
     using G = Geo<DIM, N, TM>;
     static constexpr int NV = Vars<EQ, DIM>::NV, NSYM = Vars<EQ, DIM>::NSYM;
@@ -253,7 +260,27 @@ struct StageLds {
     real sE[NE][EQ == 1 ? G::TN : 1];   // VEL: v_k; otherwise tensor (sym_index order), then 1/rho
     real sL[NV][G::NL];
     real sD[G::N1 * G::N1];
+    // ZM (z-march): the previous layer's upper z-face state, slot * NF1 + t
+    real sZ[NV][ZM ? G::NS * G::NF1 : 1];
 };
+
+// Whether the single-solve 3-D stage kernel keeps each layer's upper z-face
+// state in LDS for the next layer of its chunk (a z-marching workgroup runs
+// consecutive layers of one tile column; without the buffer the lower faces
+// read the layer below from global memory, which the same workgroup has just
+// loaded): for every 3-D class whose workgroups per CU do not drop with the
+// extra buffer. Workgroups per CU: the smaller of the LDS limit (160 KB per
+// CU) and the register target (`waves` waves per SIMD, four SIMDs).
+template <typename real, int DIM, int N, int EQ, int TM, bool VEL, int WAVES>
+constexpr bool stage_zm()
+{
+    constexpr long lds = 160 * 1024;
+    constexpr long wg_waves = Geo<DIM, N, TM>::THREADS / 64;
+    constexpr long cap = 4 * WAVES / wg_waves;
+    constexpr long with = lds / (long)sizeof(StageLds<real, DIM, N, EQ, TM, VEL, true>);
+    constexpr long without = lds / (long)sizeof(StageLds<real, DIM, N, EQ, TM, VEL, false>);
+    return DIM == 3 && (with < cap ? with : cap) == (without < cap ? without : cap);
+}
 
 // per-thread constants of a workgroup (independent of the tile)
 template <int DIM, int N, int TM>
@@ -273,44 +300,14 @@ struct ThreadSetup {
     }
 };
 
-// One tile (EPB x EPY elements) of one RHS + RK stage: tile L of
-// the solve described by p, in that solve's tile numbering. NIN >= 0 fixes the
-// number of RK inputs (p.nin) at compile time, so their loads are issued in
-// phase 1 behind the outside traces with exact waits; NIN = -1 reads p.nin and
-// loads the inputs in phase 3.
-template <typename real, int DIM, int N, int EQ, bool BUF, int TM, bool XIN = false, int NIN = -1,
-          int WAVES = 4, bool VEL = false>
-__device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
-                                           StageLds<real, DIM, N, EQ, TM, VEL> &lds,
-                                           const ThreadSetup<DIM, N, TM> &ts, real dval,
-                                           const ExtraIn *x = nullptr)
+// Tile coordinates of tile (unit) L in the launch order: x-tile, y-tile and
+// z (the layer, or for a z-marching launch the chunk of layers) from the
+// host's magic-number reciprocals: x-tile within an x-block fastest, then z
+// within a slab, then y-tile, then slab, then x-block (3-D).
+template <int DIM>
+__device__ __forceinline__ void decode_tile(const StageParams &p, uint32_t L, int64_t &tx, int64_t &ty,
+                                            int64_t &ez)
 {
-    using G = Geo<DIM, N, TM>;
-    constexpr int N1 = G::N1, NP = G::NP, NF1 = G::NF1, EPB = G::EPB, EPY = G::EPY, NS = G::NS;
-    constexpr int THREADS = G::THREADS, NF = G::NF;
-    constexpr int NV = Vars<EQ, DIM>::NV;
-    constexpr real INVW0 = real(N * (N + 1)) / real(2);     // 1/w_0 = 1/w_N
-    using A = Arr<real, BUF>;
-    using idx_t = typename A::idx_t;
-    auto &sY = lds.sY;
-    auto &sE = lds.sE;
-    constexpr int NSYM = Vars<EQ, DIM>::NSYM;
-    auto &sL = lds.sL;
-    auto &sD = lds.sD;
-    const int tid = ts.tid, slot = ts.slot, n = ts.n;
-    const int *ijk = ts.ijk;
-
-    const A yin(p.yin, p.stride, NV);
-    real par[3], rdx2[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        par[d] = real(p.par[d]);
-        rdx2[d] = real(p.rdx2[d]);
-    }
-    const real c2 = par[0] * par[0];
-    const int64_t K0 = p.K[0], K1 = p.K[1], K2 = p.K[2];
-
-    int64_t tx, ty, ez;
     if constexpr (DIM == 1) {
         tx = L; ty = 0; ez = 0;
     } else if constexpr (DIM == 2) {
@@ -327,6 +324,50 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
         ez = int64_t(r3 - r4 * p.fd_nslab.div) * p.fd_slab.div + zs;
         tx = int64_t(r4) * p.fd_xb.div + xi;
     }
+}
+
+// One tile (EPB x EPY elements) of one RHS + RK stage: the tile at x-tile tx,
+// y-tile ty, layer ez of the solve described by p. NIN >= 0 fixes the
+// number of RK inputs (p.nin) at compile time, so their loads are issued in
+// phase 1 behind the outside traces with exact waits; NIN = -1 reads p.nin and
+// loads the inputs in phase 3. ZM: z-marching kernel; zl: the layer below
+// was the previous tile of this workgroup, so the lower z-faces take the
+// other side's state from lds.sZ (written by that tile) instead of global
+// memory, and this tile leaves its upper z-face state there in turn.
+template <typename real, int DIM, int N, int EQ, bool BUF, int TM, bool XIN = false, int NIN = -1,
+          int WAVES = 4, bool VEL = false, bool ZM = false>
+__device__ __forceinline__ void stage_tile_at(const StageParams &p, int64_t tx, int64_t ty, int64_t ez,
+                                              bool zl, StageLds<real, DIM, N, EQ, TM, VEL, ZM> &lds,
+                                              const ThreadSetup<DIM, N, TM> &ts, real dval,
+                                              const ExtraIn *x = nullptr)
+{
+    using G = Geo<DIM, N, TM>;
+    constexpr int N1 = G::N1, NP = G::NP, NF1 = G::NF1, EPB = G::EPB, EPY = G::EPY, NS = G::NS;
+    constexpr int THREADS = G::THREADS, NF = G::NF;
+    constexpr int NV = Vars<EQ, DIM>::NV;
+    constexpr int ES = NP * NV;      // values per element (element-interleaved layout)
+    constexpr real INVW0 = real(N * (N + 1)) / real(2);     // 1/w_0 = 1/w_N
+    using A = Arr<real, BUF>;
+    using idx_t = typename A::idx_t;
+    auto &sY = lds.sY;
+    auto &sE = lds.sE;
+    constexpr int NSYM = Vars<EQ, DIM>::NSYM;
+    auto &sL = lds.sL;
+    auto &sD = lds.sD;
+    const int tid = ts.tid, slot = ts.slot, n = ts.n;
+    const int *ijk = ts.ijk;
+
+    const A yin(p.yin, p.stride, NV, NP);
+    real par[3], rdx2[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        par[d] = real(p.par[d]);
+        rdx2[d] = real(p.rdx2[d]);
+    }
+    const real c2 = par[0] * par[0];
+    const int64_t K0 = p.K[0], K1 = p.K[1], K2 = p.K[2];
+
+    (void)zl;
     const int64_t ex0 = tx * EPB, ey0 = ty * EPY;
     const int nact = (int)((K0 - ex0) < EPB ? (K0 - ex0) : EPB);      // active x slots
     const int nacty = EPY == 1 ? 1 : (int)((K1 - ey0) < EPY ? (K1 - ey0) : EPY);     // active rows
@@ -341,17 +382,17 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
     auto wrap = [](int64_t e, int64_t K) { return e < 0 ? e + K : (e >= K ? e - K : e); };
     // named values, not an array: a select over array elements becomes a
     // dynamically indexed (scratch) load
-    const idx_t nb0 = idx_t((ebase + wrap(ex0 - 1, K0)) * NP);
-    const idx_t nb1 = idx_t((ebase + wrap(ex0 + nact, K0)) * NP);
-    const idx_t rstride = idx_t(K0 * NP);
+    const idx_t nb0 = idx_t((ebase + wrap(ex0 - 1, K0)) * ES);
+    const idx_t nb1 = idx_t((ebase + wrap(ex0 + nact, K0)) * ES);
+    const idx_t rstride = idx_t(K0 * ES);
     idx_t nb2 = 0, nb3 = 0, nb4 = 0, nb5 = 0;
     if constexpr (DIM > 1) {
-        nb2 = idx_t((ex0 + K0 * (wrap(ey0 - 1, K1) + K1 * ez)) * NP);
-        nb3 = idx_t((ex0 + K0 * (wrap(ey0 + nacty, K1) + K1 * ez)) * NP);
+        nb2 = idx_t((ex0 + K0 * (wrap(ey0 - 1, K1) + K1 * ez)) * ES);
+        nb3 = idx_t((ex0 + K0 * (wrap(ey0 + nacty, K1) + K1 * ez)) * ES);
     }
     if constexpr (DIM > 2) {
-        nb4 = idx_t((ex0 + K0 * (ey0 + K1 * wrap(ez - 1, K2))) * NP);
-        nb5 = idx_t((ex0 + K0 * (ey0 + K1 * wrap(ez + 1, K2))) * NP);
+        nb4 = idx_t((ex0 + K0 * (ey0 + K1 * wrap(ez - 1, K2))) * ES);
+        nb5 = idx_t((ex0 + K0 * (ey0 + K1 * wrap(ez + 1, K2))) * ES);
     }
     // Face point fields (see dg_tables.cpp): w0 = d | other_is_lower << 2 |
     // bsel << 3 | other_in_tile << 6 | row << 7 | need << 8 | xplane << 16 |
@@ -383,12 +424,19 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
         return idx_t(b) + idx_t(w2);
     };
 
+    // lower z-face point whose other side (the layer below) is in lds.sZ
+    auto z_in_lds = [zl](uint32_t w0) {
+        (void)zl;
+        if constexpr (!ZM) return false;
+        else return zl && (w0 & 3u) == 2u && ((w0 >> 2) & 1u);
+    };
+
     // ---- phase 1: state, 1/rho and flux tensor into LDS; the outside trace
     // of this thread's first face point is prefetched behind the own state.
     const bool active = EPY == 1 ? slot < nact : ts.sx < nact && ts.sy < nacty;
     const int ln = slot * NP + n;
-    const idx_t gi = EPY == 1 ? idx_t((ebase + ex0 + slot) * NP + n)
-                              : idx_t((ebase + K0 * ts.sy + ex0 + ts.sx) * NP + n);
+    const idx_t gi = EPY == 1 ? idx_t((ebase + ex0 + slot) * ES + n)
+                              : idx_t((ebase + K0 * ts.sy + ex0 + ts.sx) * ES + n);
     // both groups are loaded unconditionally (inactive lanes read node 0) so
     // the wait before the LDS stores covers only the first group
     // Issue order matters (vector loads retire in order): this thread's first
@@ -416,13 +464,13 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
     const idx_t gy = active ? gi : idx_t(0);
 #pragma unroll
     for (int v = 0; v < NV; ++v) y[v] = yin.ld(v, gy);
-    const bool pre = tid < NF && face_valid(fw0) && other_outside(fw0);
+    const bool pre = tid < NF && face_valid(fw0) && other_outside(fw0) && !z_in_lds(fw0);
     const idx_t gn0 = pre ? outside_node(fw0, fw2) : idx_t(0);
 #pragma unroll
     for (int v = 0; v < NV; ++v) g[v] = yin.ld(v, gn0);
     real g2[NV];
     if constexpr (PASS2) {
-        const bool pre2 = tid + THREADS < NF && face_valid(fx0) && other_outside(fx0);
+        const bool pre2 = tid + THREADS < NF && face_valid(fx0) && other_outside(fx0) && !z_in_lds(fx0);
         const idx_t gn2 = pre2 ? outside_node(fx0, fx2) : idx_t(0);
 #pragma unroll
         for (int v = 0; v < NV; ++v) g2[v] = yin.ld(v, gn2);
@@ -433,12 +481,12 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
     constexpr bool EARLY = NIN >= 0 && WAVES == 4;
     real a0[NV], a1[NV];
     if constexpr (EARLY && NIN >= 1) {
-        const A in0(p.in0, p.stride, NV);
+        const A in0(p.in0, p.stride, NV, NP);
 #pragma unroll
         for (int v = 0; v < NV; ++v) a0[v] = in0.ld(v, gy);
     }
     if constexpr (EARLY && NIN >= 2) {
-        const A in1(p.in1, p.stride, NV);
+        const A in1(p.in1, p.stride, NV, NP);
 #pragma unroll
         for (int v = 0; v < NV; ++v) a1[v] = in1.ld(v, gy);
     }
@@ -489,10 +537,20 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
         }
         if (!face_valid(w0)) continue;
         const bool oglob = other_outside(w0);
-        if (f >= 2 * THREADS && oglob) {
+        const bool ozl = z_in_lds(w0);
+        if (f >= 2 * THREADS && oglob && !ozl) {
             const idx_t gn = outside_node(w0, w2);
 #pragma unroll
             for (int v = 0; v < NV; ++v) g[v] = yin.ld(v, gn);
+        }
+        if constexpr (ZM) {
+            // the layer below's upper face node, left in LDS by the previous
+            // tile of this workgroup (slot * NF1 + t: the table's other-lift
+            // field of a lower z-face point)
+            if (ozl) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) g[v] = lds.sZ[v][w3 >> 16];
+            }
         }
         const int own_q = int(w1 & 0xffffu);
         const int oth_q = int(w1 >> 16);
@@ -598,13 +656,20 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
                 for (int v = 0; v < NV; ++v) R[v] += sL[v][li];
             }
         }
+        if constexpr (ZM) {
+            // this layer's upper z-face state, for the next layer's lower faces
+            if (ijk[2] == N) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) lds.sZ[v][slot * NF1 + ijk[0] + N1 * ijk[1]] = y[v];
+            }
+        }
         if (!EARLY && has0) {
-            const A in0(p.in0, p.stride, NV);
+            const A in0(p.in0, p.stride, NV, NP);
 #pragma unroll
             for (int v = 0; v < NV; ++v) a0[v] = in0.ld(v, gi);
         }
         if (!EARLY && has1) {
-            const A in1(p.in1, p.stride, NV);
+            const A in1(p.in1, p.stride, NV, NP);
 #pragma unroll
             for (int v = 0; v < NV; ++v) a1[v] = in1.ld(v, gi);
         }
@@ -617,7 +682,7 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
             if (o < p.nout) {
                 const real cy = real(p.cy[o]), c0 = real(p.c0[o]), c1 = real(p.c1[o]),
                            cr = real(p.cr[o]);
-                const A out(o == 0 ? p.out0 : p.out1, p.stride, NV);
+                const A out(o == 0 ? p.out0 : p.out1, p.stride, NV, NP);
                 if constexpr (!XIN) {
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
@@ -638,7 +703,7 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
                     for (int j = 0; j < x->n; ++j) {
                         if (x->c[o][j] == 0.0) continue;
                         const real cj = real(x->c[o][j]);
-                        const A in(x->in[j], p.stride, NV);
+                        const A in(x->in[j], p.stride, NV, NP);
 #pragma unroll
                         for (int v = 0; v < NV; ++v) val[v] = fmadd(cj, in.ld(v, gi), val[v]);
                     }
@@ -650,6 +715,25 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
     }
 }
 
+// stage_tile_at on tile L of the launch order (one layer per tile)
+template <typename real, int DIM, int N, int EQ, bool BUF, int TM, bool XIN = false, int NIN = -1,
+          int WAVES = 4, bool VEL = false>
+__device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
+                                           StageLds<real, DIM, N, EQ, TM, VEL> &lds,
+                                           const ThreadSetup<DIM, N, TM> &ts, real dval,
+                                           const ExtraIn *x = nullptr)
+{
+    int64_t tx, ty, ez;
+    decode_tile<DIM>(p, L, tx, ty, ez);
+    stage_tile_at<real, DIM, N, EQ, BUF, TM, XIN, NIN, WAVES, VEL>(p, tx, ty, ez, false, lds, ts, dval, x);
+}
+
+// Single-solve stage kernel. Virtual block b is unit L of the launch order
+// (XCD-contiguous renumbering: b runs on XCD b % 8): the chunk of p.zlen
+// layers (1 in 1-D and 2-D) of one tile column that decode_tile's z
+// coordinate names, run bottom to top (z-march). Classes with stage_zm take
+// the lower z-faces' other side of every layer after the chunk's first from
+// the LDS copy of the layer below.
 template <typename real, int DIM, int N, int EQ, bool BUF, int NIN, int TM = 1>
 __global__ void __launch_bounds__((Geo<DIM, N, TM>::THREADS))
 __attribute__((amdgpu_waves_per_eu(stage_waves(DIM, N, EQ, (int)sizeof(real), BUF))))
@@ -658,15 +742,24 @@ stage_kernel(const StageParams p)
     using G = Geo<DIM, N, TM>;
     constexpr int W = stage_waves(DIM, N, EQ, (int)sizeof(real), BUF);
     constexpr bool VEL = stage_vel(DIM, N, EQ, (int)sizeof(real), BUF);
-    __shared__ StageLds<real, DIM, N, EQ, TM, VEL> lds;
+    constexpr bool ZM = stage_zm<real, DIM, N, EQ, TM, VEL, W>();
+    __shared__ StageLds<real, DIM, N, EQ, TM, VEL, ZM> lds;
     const ThreadSetup<DIM, N, TM> ts;
     const real dval = ts.tid < G::N1 * G::N1 ? static_cast<const real *>(p.D)[ts.tid] : real(0);
     for (uint32_t vb = blockIdx.x; vb < p.ntiles32; vb += gridDim.x) {
-        // tile number: XCD-contiguous renumbering of the virtual block
         const uint32_t xb = vb & (kXcds - 1), jb = vb / kXcds;
         const uint32_t L = p.plain_order ? vb : xb * p.xq + (xb < p.xr ? xb : p.xr) + jb;
-        stage_tile<real, DIM, N, EQ, BUF, TM, false, NIN, W, VEL>(p, L, lds, ts, dval);
-        __syncthreads();
+        int64_t tx, ty, ez;
+        decode_tile<DIM>(p, L, tx, ty, ez);
+        // (32-bit: K_z <= 2^30)
+        const uint32_t z0 = uint32_t(ez) * p.zlen;
+        const uint32_t kz = uint32_t(p.K[2]);
+        const uint32_t z1 = z0 + p.zlen < kz ? z0 + p.zlen : kz;
+        for (uint32_t z = z0; z < z1; ++z) {
+            stage_tile_at<real, DIM, N, EQ, BUF, TM, false, NIN, W, VEL, ZM>(p, tx, ty, z, ZM && z > z0, lds,
+                                                                           ts, dval);
+            __syncthreads();
+        }
     }
 }
 

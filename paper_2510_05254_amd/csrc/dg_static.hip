@@ -4,7 +4,8 @@
 // harnesses that forbid hipMalloc).
 //
 // The work memory of dg_step -- the operator tables (D, w, face-point
-// descriptors) and the Runge-Kutta work arrays -- comes from `scratch`, a
+// descriptors), the Runge-Kutta work arrays and, for more than one
+// variable, the element-interleaved copy of the state -- comes from `scratch`, a
 // fixed file-scope device array. Each GPU the library runs on holds its own
 // copy until the process ends. In host code `scratch` names a host-side
 // stand-in, so its device address is looked up once per device (with that
@@ -30,8 +31,8 @@ static_assert(kStaticScratch % kAlign == 0, "scratch size must be a multiple of 
 static __device__ __align__(256) unsigned char scratch[DG_STATIC_SCRATCH_BYTES];
 
 // Per device: the scratch array's device address, and which operator tables
-// (dim, N, precision) it holds now, so a run of calls of one kernel class
-// uploads them once.
+// (dim, N, equation, precision) it holds now, so a run of calls of one kernel
+// class uploads them once.
 constexpr int kMaxDevices = 64;
 struct DeviceScratch {
     char *ptr = nullptr;
@@ -40,7 +41,7 @@ struct DeviceScratch {
 std::mutex g_mu;
 DeviceScratch g_dev[kMaxDevices];
 
-int table_key(int dim, int N, int prec) { return dim + 4 * (N + 16 * prec); }
+int table_key(int dim, int N, int eq, int prec) { return dim + 4 * (N + 16 * (eq + 2 * prec)); }
 
 // The device address of `scratch` on the current device (looked up once).
 int scratch_on(int device, char **ptr)
@@ -82,7 +83,10 @@ extern "C" int dg_step_static(int dim, int N, const int64_t *K, int equation, co
     if ((rc = setup_solver(&h, dim, N, K, equation, params, precision))) return rc;
     if (count != h.unknowns)
         return fail(DG_EINVAL, "count must equal nvar * nodes = " + std::to_string(h.unknowns));
-    const size_t need = h.lay.tables + (rk == DG_RK6 ? 8 : 3) * h.lay.array;
+    // the device layout interleaves an element's variables: with more than
+    // one variable the state is converted into a scratch array and back
+    const bool conv = h.nvar > 1;
+    const size_t need = h.lay.tables + ((rk == DG_RK6 ? 8 : 3) + (conv ? 1 : 0)) * h.lay.array;
     if (need > kStaticScratch)
         return fail(DG_ENOMEM, "dg_step_static: this problem needs " + std::to_string(need) +
                                    " bytes of work memory; the static scratch holds " +
@@ -98,14 +102,22 @@ extern "C" int dg_step_static(int dim, int N, const int64_t *K, int equation, co
     char *base = nullptr;
     if ((rc = scratch_on(h.device, &base))) return rc;
     char *arrays = carve_tables(&h, base);
-    h.U = u_dev;
+    if (conv) {
+        h.U = arrays;
+        arrays += h.lay.array;
+    } else {
+        h.U = u_dev;
+    }
     carve_rk_arrays(&h, arrays, rk == DG_RK6);
-    const int key = table_key(dim, N, precision);
+    const int key = table_key(dim, N, equation, precision);
     if (g_dev[h.device].table_key != key) {
         g_dev[h.device].table_key = -1;
         if ((rc = upload_tables(&h))) return rc;
         g_dev[h.device].table_key = key;
     }
     h.has_state = true;
-    return enqueue_steps(&h, rk, dt, nsteps);
+    if (conv && (rc = convert(&h, u_dev, precision, h.U, precision, true))) return rc;
+    if ((rc = enqueue_steps(&h, rk, dt, nsteps))) return rc;
+    if (conv && (rc = convert(&h, h.U, precision, u_dev, precision, false))) return rc;
+    return DG_OK;
 }

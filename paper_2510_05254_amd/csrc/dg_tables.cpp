@@ -26,9 +26,15 @@
 //        row:    the outside element lies in tile row 1 (x and z faces): one
 //                row of elements further than the base (so EPY <= 2);
 //   w1 = own_q | other_q << 16   tile node index (slot * Np + node) of each side
-//   w2 = goff                    node offset of an outside other side from its
-//                                base (x: node; y, z: sx * Np + node)
-//   w3 = own_lift | other_lift << 16   lift slots of the two sides
+//   w2 = goff                    value offset of an outside other side from its
+//                                base in the element-interleaved state arrays
+//                                (x: node; y, z: sx * nv * Np + node)
+//   w3 = own_lift | other_lift << 16   lift slots of the two sides; for a
+//                                lower z-face point (other side outside the
+//                                tile, no lift) other_lift is instead the
+//                                point's index slot * NF1 + t in the
+//                                z-marching kernel's buffer of the layer
+//                                below's upper-face state
 #include <cstdint>
 #include <vector>
 
@@ -66,10 +72,11 @@ void put(const FacePoint &p, uint32_t *e)
 
 }  // namespace
 
-void build_face_table(int dim, int N, int epb, int epy, uint32_t *tab)
+void build_face_table(int dim, int N, int epb, int epy, int nv, uint32_t *tab)
 {
     const int N1 = N + 1, NF1 = ipow_h(N1, dim - 1);
     const uint32_t NP = (uint32_t)ipow_h(N1, dim);
+    const uint32_t ES = NP * (uint32_t)nv;       // values per element in the state arrays
     const int ns = epb * epy;
     auto slot = [&](int sx, int sy) { return (uint32_t)(sx + epb * sy); };
     auto lift = [&](int d, uint32_t s, int side, int t) {
@@ -124,13 +131,13 @@ void build_face_table(int dim, int N, int epb, int epy, uint32_t *tab)
                         p.own_lift = lift(1, slot(sx, 0), 0, t);
                         p.oth_lower = 1;
                         p.bsel = 2;
-                        p.goff = (uint32_t)sx * NP + nhi;
+                        p.goff = (uint32_t)sx * ES + nhi;
                     } else {          // own: row py-1 (lower side), other: row py or outside
                         p.own_q = slot(sx, py - 1) * NP + nhi;
                         p.own_lift = lift(1, slot(sx, py - 1), 1, t);
                         p.oth_lower = 0;
                         p.bsel = 3;
-                        p.goff = (uint32_t)sx * NP + nlo;
+                        p.goff = (uint32_t)sx * ES + nlo;
                         if (py < epy) {
                             p.in_tile = 1;
                             p.yplane = (uint32_t)py;
@@ -156,7 +163,8 @@ void build_face_table(int dim, int N, int epb, int epy, uint32_t *tab)
                         p.own_lift = lift(2, slot(sx, sy), side, t);
                         p.oth_lower = side == 0 ? 1 : 0;
                         p.bsel = side == 0 ? 4 : 5;
-                        p.goff = (uint32_t)sx * NP + (side == 0 ? nhi : nlo);
+                        p.goff = (uint32_t)sx * ES + (side == 0 ? nhi : nlo);
+                        if (side == 0) p.oth_lift = slot(sx, sy) * (uint32_t)NF1 + (uint32_t)t;
                         put(p, e);
                     }
 }

@@ -207,7 +207,13 @@ class Server:
         blk = self.arena.alloc(ws)
         if blk is None:
             return False
-        s = dg.Solver(r.dim, r.N, r.K, r.eq, r.params, hip_stream=self.stream.cuda_stream,
+        # each admitted solver gets a stream of its own (hip_stream=None):
+        # creating it and setting its state wait for that fresh stream only,
+        # not for the ticks in flight on the batch stream, which dg_batch_add
+        # orders after the member's stream (a stream shared by all members
+        # would wait for every run, since each run makes member streams
+        # wait for the batch)
+        s = dg.Solver(r.dim, r.N, r.K, r.eq, r.params, precision=dg.DG_FP64, hip_stream=None,
                       device_workspace=self.arena.base + blk[0], workspace_bytes=blk[1])
         s._ws = self.arena.buf                  # the arena outlives the solver
         s.set_state(U0)

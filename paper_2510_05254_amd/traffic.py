@@ -70,7 +70,8 @@ def main():
     ap.add_argument("--command", default="", help="the profiled command, recorded as is")
     ap.add_argument("--rk", type=int, default=4, help="RK scheme of the profiled run")
     ap.add_argument("--launch-config", default=None,
-                    help="tile order, z-slab, x-block of the profiled run (bench.py's launch_config)")
+                    help="tile order, z-slab, x-block, z-march length of the profiled run "
+                         "(bench.py's launch_config)")
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
     f = reduce(a.fetch, "FETCH_SIZE", a.kernel)

@@ -27,7 +27,7 @@ STUB = """#pragma once
 #include <cstdint>
 namespace dg {
 int face_table_size(int dim, int N, int epb, int epy);
-void build_face_table(int dim, int N, int epb, int epy, uint32_t *tab);
+void build_face_table(int dim, int N, int epb, int epy, int nv, uint32_t *tab);
 }
 """
 DUMP = """#include <cstdio>
@@ -36,9 +36,10 @@ DUMP = """#include <cstdio>
 #include "dg_host.hpp"
 int main(int argc, char **argv) {
     const int dim = atoi(argv[1]), N = atoi(argv[2]), epb = atoi(argv[3]), epy = atoi(argv[4]);
+    const int nv = atoi(argv[5]);
     const int n = dg::face_table_size(dim, N, epb, epy);
     std::vector<uint32_t> t(4 * (size_t)n);
-    dg::build_face_table(dim, N, epb, epy, t.data());
+    dg::build_face_table(dim, N, epb, epy, nv, t.data());
     for (int f = 0; f < n; ++f) printf("%u %u %u %u\\n", t[4 * f], t[4 * f + 1], t[4 * f + 2], t[4 * f + 3]);
     return 0;
 }
@@ -57,8 +58,8 @@ def dump(tmp_path_factory):
     subprocess.run(["g++", "-O1", "-std=c++17", "-o", str(exe), str(d / "dump.cpp"), str(d / "dg_tables.cpp")],
                    check=True, capture_output=True)
 
-    def table(dim, N, epb, epy):
-        out = subprocess.run([str(exe), str(dim), str(N), str(epb), str(epy)], check=True,
+    def table(dim, N, epb, epy, nv=1):
+        out = subprocess.run([str(exe), str(dim), str(N), str(epb), str(epy), str(nv)], check=True,
                              capture_output=True, text=True).stdout
         return [tuple(int(x) for x in line.split()) for line in out.splitlines()]
     return table
@@ -70,16 +71,20 @@ def tile_shape(dim, N):
     return epb, 2 if (dim == 3 and N == 4) else 1
 
 
-def emulate(tab, dim, N, K, epb, epy):
-    """Walk every tile as the face phase does; return the set of written lifts."""
+def emulate(tab, dim, N, K, epb, epy, nv=1):
+    """Walk every tile as the face phase does; return the set of written lifts.
+    Global indices are those of the element-interleaved state arrays (element
+    stride nv * Np values; variable 0 of node n of element e at e * nv * Np + n)."""
     N1 = N + 1
     NP, NF1, NS = N1 ** dim, N1 ** (dim - 1), epb * epy
+    ES = nv * NP
     K0, K1, K2 = (tuple(K) + (1, 1))[:3]
     nodes = K0 * K1 * K2 * NP
     wrap = lambda e, k: (e + k) % k
 
-    def where(g):                     # global node -> element (ex, ey, ez), node (i, j, k)
-        e, n = divmod(g, NP)
+    def where(g):                     # global value index -> element (ex, ey, ez), node (i, j, k)
+        e, n = divmod(g, ES)
+        assert n < NP, "index is not variable 0 of a node"
         return (e % K0, (e // K0) % K1, e // (K0 * K1)), (n % N1, (n // N1) % N1, n // (N1 * N1))
 
     def lift_slot(q, d, side):        # the slot the node-parallel phase reads
@@ -95,17 +100,17 @@ def emulate(tab, dim, N, K, epb, epy):
                 ex0, ey0 = tx * epb, ty * epy
                 nact, nacty = min(epb, K0 - ex0), min(epy, K1 - ey0)
                 ebase = K0 * (ey0 + K1 * ez)
-                nb = [(ebase + wrap(ex0 - 1, K0)) * NP, (ebase + wrap(ex0 + nact, K0)) * NP,
-                      (ex0 + K0 * (wrap(ey0 - 1, K1) + K1 * ez)) * NP,
-                      (ex0 + K0 * (wrap(ey0 + nacty, K1) + K1 * ez)) * NP,
-                      (ex0 + K0 * (ey0 + K1 * wrap(ez - 1, K2))) * NP,
-                      (ex0 + K0 * (ey0 + K1 * wrap(ez + 1, K2))) * NP]
+                nb = [(ebase + wrap(ex0 - 1, K0)) * ES, (ebase + wrap(ex0 + nact, K0)) * ES,
+                      (ex0 + K0 * (wrap(ey0 - 1, K1) + K1 * ez)) * ES,
+                      (ex0 + K0 * (wrap(ey0 + nacty, K1) + K1 * ez)) * ES,
+                      (ex0 + K0 * (ey0 + K1 * wrap(ez - 1, K2))) * ES,
+                      (ex0 + K0 * (ey0 + K1 * wrap(ez + 1, K2))) * ES]
 
                 def in_tile(q):
                     s, n = divmod(q, NP)
                     sy, sx = divmod(s, epb)
                     assert sx < nact and sy < nacty, "in-tile side on an inactive slot"
-                    return (ebase + K0 * sy + ex0 + sx) * NP + n
+                    return (ebase + K0 * sy + ex0 + sx) * ES + n
 
                 for w0, w1, w2, w3 in tab:
                     if not ((w0 >> 8) & 0xff) <= nact or not ((w0 >> 24) & 0xf) <= nacty:
@@ -114,8 +119,8 @@ def emulate(tab, dim, N, K, epb, epy):
                     outside = ((w0 >> 6) & 1) == 0 or ((w0 >> 16) & 0xff) == nact or (w0 >> 28) == nacty
                     own_q, oth_q, own_l, oth_l = w1 & 0xffff, w1 >> 16, w3 & 0xffff, w3 >> 16
                     g_own = in_tile(own_q)
-                    g_oth = nb[bsel] + ((w0 >> 7) & 1) * K0 * NP + w2 if outside else in_tile(oth_q)
-                    assert 0 <= g_oth < nodes, "outside read out of bounds"
+                    g_oth = nb[bsel] + ((w0 >> 7) & 1) * K0 * ES + w2 if outside else in_tile(oth_q)
+                    assert 0 <= g_oth < nodes * nv, "outside read out of bounds"
                     (e_o, n_o), (e_t, n_t) = where(g_own), where(g_oth)
                     (e_lo, n_lo), (e_hi, n_hi) = ((e_t, n_t), (e_o, n_o)) if oth_lower else ((e_o, n_o), (e_t, n_t))
                     assert e_hi[d] == wrap(e_lo[d] + 1, (K0, K1, K2)[d]), "sides are not neighbours"
@@ -127,6 +132,13 @@ def emulate(tab, dim, N, K, epb, epy):
                     key = (g_own, d, own_side)
                     assert key not in lifts, "lift written twice"
                     lifts.add(key)
+                    if d == 2 and oth_lower:
+                        # z-marching kernels read the layer below's upper face
+                        # from their LDS buffer at slot * NF1 + t, where the
+                        # layer below stored node (i, j, N) of the same slot
+                        s_own, n_own = divmod(own_q, NP)
+                        assert oth_l == s_own * NF1 + n_own, "z-march buffer index"
+                        assert n_own < NF1
                     if not outside:
                         assert oth_l == lift_slot(oth_q, d, 1 - own_side)
                         key = (g_oth, d, 1 - own_side)
@@ -134,7 +146,7 @@ def emulate(tab, dim, N, K, epb, epy):
                         lifts.add(key)
     # every face node of every element, once per direction and side
     want = set()
-    for g in range(nodes):
+    for g in (e * ES + n for e in range(K0 * K1 * K2) for n in range(NP)):
         _, ijk = where(g)
         for d in range(dim):
             if ijk[d] == 0:
@@ -160,9 +172,10 @@ def test_kernel_tile_tables(dump, dim, N):
         meshes_ = [(1, 1, 1), (2, 3, 2), (3, 1, 2)]        # keep the emulation small
     else:
         meshes_ = meshes(dim, epb, epy)
-    tab = dump(dim, N, epb, epy)
-    for K in meshes_:
-        emulate(tab, dim, N, K, epb, epy)
+    for nv in (1, 1 + dim):                                 # advection, isothermal Euler
+        tab = dump(dim, N, epb, epy, nv)
+        for K in meshes_:
+            emulate(tab, dim, N, K, epb, epy, nv)
 
 
 # The builder for tile shapes the kernels do not use (two rows in 2-D, other
@@ -172,7 +185,8 @@ def test_kernel_tile_tables(dump, dim, N):
     (3, 3, 4, 2, (5, 3, 2)), (3, 2, 2, 2, (3, 5, 2)), (3, 4, 1, 2, (3, 3, 1)), (3, 4, 2, 1, (5, 3, 2)),
 ])
 def test_other_tile_shapes(dump, dim, N, epb, epy, K):
-    emulate(dump(dim, N, epb, epy), dim, N, K, epb, epy)
+    for nv in (1, 1 + dim):
+        emulate(dump(dim, N, epb, epy, nv), dim, N, K, epb, epy, nv)
 
 
 def test_table_sizes(dump):
@@ -183,3 +197,11 @@ def test_table_sizes(dump):
             (epb * epy * 2 * nf1 if dim > 2 else 0)
         assert len(dump(dim, N, epb, epy)) == want
         assert 16 * want <= 16384          # the library's face-table budget
+
+
+def test_emulation_rejects_a_table_for_another_layout(dump):
+    """The y/z outside offsets depend on the values per element: a table built
+    for one variable, read with the Euler layout's element stride, must fail."""
+    epb, epy = tile_shape(3, 4)
+    with pytest.raises(AssertionError):
+        emulate(dump(3, 4, epb, epy, 1), 3, 4, (epb + 1, 3, 2), epb, epy, 4)

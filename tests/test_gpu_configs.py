@@ -100,6 +100,25 @@ def test_config_full_run_parity(cid):
         assert r < 1e-8, r
 
 
+# RK3 (Heun) and the fused RK6 at the configurations' full sizes: several
+# steps of each against the oracle (the fixed-step runs use RK4).
+@pytest.mark.parametrize("cid,rk,nsteps", [(2, 3, 20), (2, 6, 10), (3, 3, 20), (3, 6, 8),
+                                           (4, 3, 5), (4, 6, 3)])
+def test_config_rk3_rk6_parity(cid, rk, nsteps):
+    w, ax, U0, dt, n = _inputs(cid)
+    _say(f"config {cid}: {nsteps} RK{rk} steps")
+    with dg.Solver(w.dim, w.N, w.K, w.eq, w.params) as s:
+        s.set_state(U0)
+        s.step(rk, dt, nsteps)
+        Ug = s.get_state()
+    t0 = time.perf_counter()
+    Uo = oracle.step(w.dim, w.N, w.K, w.eq, w.params, U0, rk, dt, nsteps)
+    _say(f"config {cid} RK{rk}: oracle {time.perf_counter() - t0:.1f} s")
+    l2, el = parity(Ug, Uo, what=f"config {cid} RK{rk}, {nsteps} steps")
+    _say(f"config {cid} RK{rk}, {nsteps} steps: rel L2 per var {l2}, elementwise {el}")
+    assert rel_l2_per_var(Uo, U0).max() > 1e3 * PARITY_RTOL
+
+
 # FP32 path at the configurations' sizes and full step counts against the
 # FP64 oracle. Single precision rounds each stage operation at u = 6e-8; the
 # error may grow linearly with the number of stages (400, 800 and 200 for

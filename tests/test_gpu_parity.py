@@ -37,11 +37,12 @@ def test_parity_rk4(dim, N, eq):
 
 
 @pytest.mark.parametrize("rk", [3, 6])
-@pytest.mark.parametrize("dim,N,eq", [(d, n, e) for d in (1, 2, 3) for n in (1, 4, 8) for e in (ADV, EUL)])
+@pytest.mark.parametrize("dim,N,eq", ALL)
 def test_parity_rk3_rk6(dim, N, eq, rk):
     K = ragged_K(dim, N)
-    U0, Ug, Uo = _run_both(dim, N, K, eq, rk, 2)
+    U0, Ug, Uo = _run_both(dim, N, K, eq, rk, 3)
     parity(Ug, Uo, what=f"rk={rk} dim={dim} N={N} eq={eq}")
+    assert rel_l2_per_var(Uo, U0).max() > 1e3 * PARITY_RTOL
 
 
 @pytest.mark.parametrize("dim,N,K,eq", [
@@ -286,40 +287,47 @@ def test_autotune_keeps_state_and_results(dim, N, K, eq, rk):
         ref = s.get_state()
         s.set_state(U0)
         cfg = s.autotune(rk, dt, 2)
-        assert cfg[3] == 1 and cfg[0] in (0, 1) and cfg[1] >= 1 and cfg[2] >= 3 and cfg[4] >= 1
+        assert cfg[3] == 1 and cfg[0] in (0, 1) and cfg[1] >= 1 and cfg[2] >= 3 and cfg[4] >= 1 and cfg[5] >= 1
         np.testing.assert_array_equal(s.get_state(), U0)
         s.step(rk, dt, 3)
         np.testing.assert_array_equal(s.get_state(), ref)
 
 
-# Every launch configuration (tile order, z-slab, x-block) visits the same
-# tiles in another order: the results are bitwise those of the default one,
-# also with a ragged last x-tile and x-blocks of one tile.
+# Every launch configuration (tile order, z-slab, x-block, z-march length)
+# visits the same tiles in another order: the results are bitwise those of the
+# default one, also with a ragged last x-tile, x-blocks of one tile, z-march
+# chunks with a ragged last chunk and whole-column chunks (the first layer's
+# lower neighbour is then the column's top layer, across the periodic wrap).
 @pytest.mark.parametrize("N,K,eq,cfgs", [
-    (4, (16, 5, 6), EUL, [(0, 1, 2), (0, 3, 4), (1, 6, 1), (0, 2, 8), (1, 1, 4)]),
-    (4, (15, 3, 4), ADV, [(0, 4, 2), (0, 1, 1), (1, 2, 4)]),
-    (1, (70, 3, 4), EUL, [(0, 2, 1), (1, 4, 3), (0, 1, 3)]),
+    (4, (16, 5, 6), EUL, [(0, 1, 2, 1), (0, 3, 4, 1), (1, 6, 1, 1), (0, 2, 8, 1), (1, 1, 4, 1),
+                          (0, 1, 4, 2), (0, 2, 2, 4), (1, 1, 8, 6), (0, 1, 4, 5), (0, 3, 1, 2)]),
+    (4, (15, 3, 4), ADV, [(0, 4, 2, 1), (0, 1, 1, 1), (1, 2, 4, 1), (0, 1, 4, 4), (0, 2, 1, 3)]),
+    (1, (70, 3, 4), EUL, [(0, 2, 1, 1), (1, 4, 3, 1), (0, 1, 3, 1), (0, 1, 1, 4), (0, 2, 3, 2)]),
+    (2, (9, 4, 7), EUL, [(0, 1, 1, 7), (0, 1, 1, 3), (1, 2, 1, 2)]),
 ])
 def test_launch_configs_bitwise(N, K, eq, cfgs):
     w, ax, U0, dt = case(3, N, K, eq, 22)
     with dg.Solver(3, N, K, eq, params(3, eq)) as s:
         base = s.launch_config()
-        assert base[3] == 0 and base[4] >= 1
+        assert base[3] == 0 and base[4] >= 1 and base[5] >= 1
         refs = {}
         for rk in (4, 3):
             s.set_state(U0)
             s.step(rk, dt, 2)
             refs[rk] = s.get_state()
-        for order, slab, xblk in cfgs:
+        for order, slab, xblk, zlen in cfgs:
             c = list(base)
-            c[0], c[1], c[4] = order, slab, xblk
+            c[0], c[1], c[4], c[5] = order, slab, xblk, zlen
             s.set_launch_config(c)
             got = s.launch_config()
-            assert (got[0], got[1], got[4], got[3]) == (order, slab, xblk, 0)
-            for rk in (4, 3):
+            assert (got[0], got[1], got[4], got[5], got[3]) == (order, slab, xblk, zlen, 0)
+            for rk in (4, 3, 6):
                 s.set_state(U0)
                 s.step(rk, dt, 2)
-                np.testing.assert_array_equal(s.get_state(), refs[rk], err_msg=f"{(order, slab, xblk)} rk{rk}")
+                if rk not in refs:
+                    refs[rk] = s.get_state()
+                np.testing.assert_array_equal(s.get_state(), refs[rk],
+                                              err_msg=f"{(order, slab, xblk, zlen)} rk{rk}")
 
 
 def test_set_launch_config_errors():
@@ -327,7 +335,7 @@ def test_set_launch_config_errors():
     with dg.Solver(3, 4, (8, 3, 6), EUL, params(3, EUL)) as s:
         base = list(s.launch_config())
         assert base[4] == 4            # 8 elements, 2 per tile
-        for i, v in ((0, 2), (0, -1), (1, 4), (1, 0), (2, 0), (2, 2000), (4, 3), (4, 0)):
+        for i, v in ((0, 2), (0, -1), (1, 4), (1, 0), (2, 0), (2, 2000), (4, 3), (4, 0), (5, 0), (5, 7)):
             c = list(base)
             c[i] = v
             with pytest.raises(dg.DgError) as e:
@@ -337,11 +345,21 @@ def test_set_launch_config_errors():
         with pytest.raises(ValueError):
             s.set_launch_config(base[:4])
         with pytest.raises(dg.DgError) as e:
-            dg._call("dg_set_launch_config", s.h, (dg.ctypes.c_int64 * 5)(*base), 4)
+            dg._call("dg_set_launch_config", s.h, (dg.ctypes.c_int64 * 6)(*base), 5)
         assert e.value.status == dg.DG_EINVAL
+        # the z-slab counts z-units: with chunks of 4 layers K_z = 6 has 2
+        c = list(base)
+        c[5], c[1] = 4, 3
+        with pytest.raises(dg.DgError) as e:
+            s.set_launch_config(c)
+        assert e.value.status == dg.DG_EINVAL
+        c[1] = 2
+        s.set_launch_config(c)
+        assert s.launch_config()[5] == 4 and s.launch_config()[1] == 2
+        s.set_launch_config(base)
     with dg.Solver(2, 3, (5, 4), ADV, params(2, ADV)) as s:
         base = list(s.launch_config())
-        for i, v in ((1, 2), (4, base[4] + 1)):
+        for i, v in ((1, 2), (4, base[4] + 1), (5, 2)):
             c = list(base)
             c[i] = v
             with pytest.raises(dg.DgError) as e:
@@ -381,3 +399,27 @@ def test_autotune_error_paths():
         with pytest.raises(dg.DgError) as e:
             s.autotune(4, dt)
         assert e.value.status == dg.DG_ENOTSUP
+
+
+# An external workspace with one state array to spare: the tuner keeps its
+# copy of the state there, restores the state, and stepping afterwards is
+# bitwise the untuned result (also for RK6, whose store precedes the copy).
+@pytest.mark.parametrize("dim,N,K,eq,rk", [(3, 4, (6, 3, 4), EUL, 4), (3, 2, (5, 4, 4), ADV, 6),
+                                           (2, 3, (9, 7), EUL, 3)])
+def test_autotune_with_external_workspace(dim, N, K, eq, rk):
+    import torch
+    w, ax, U0, dt = case(dim, N, K, eq, 23)
+    with dg.Solver(dim, N, K, eq, params(dim, eq)) as s:
+        s.set_state(U0)
+        s.step(rk, dt, 3)
+        ref = s.get_state()
+    arr = -(-U0.size * 8 // 256) * 256
+    ws = dg.dg_workspace_bytes(dim, N, K, eq, dg.DG_FP64, rk) + arr
+    buf = torch.empty(ws, dtype=torch.uint8, device="cuda")
+    with dg.Solver(dim, N, K, eq, params(dim, eq), device_workspace=buf, workspace_bytes=ws) as s:
+        s.set_state(U0)
+        cfg = s.autotune(rk, dt, 2)
+        assert cfg[3] == 1
+        np.testing.assert_array_equal(s.get_state(), U0)
+        s.step(rk, dt, 3)
+        np.testing.assert_array_equal(s.get_state(), ref)
