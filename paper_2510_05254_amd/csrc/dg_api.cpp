@@ -314,6 +314,9 @@ int setup_solver(dg_solver *h, int dim, int N, const int64_t *K, int equation, c
     if (dim == 3) {
         for (int64_t xb = std::max<int64_t>(4, h->tiles_x / kXcds); xb >= 4; --xb)
             if (h->tiles_x % xb == 0) { h->xblk = xb; break; }
+        // FP32 3-D: units of up to four layers per workgroup (z-march; -5 %
+        // per launch on 64^3 N = 4, where FP64 is fastest with one layer)
+        if (precision == DG_FP32) h->zlen = std::min<int64_t>(4, h->K[2]);
     }
     h->ntiles = h->tiles_x * h->tiles_y * h->K[2];
     h->grid = std::min<int64_t>(h->ntiles, kMaxGrid);

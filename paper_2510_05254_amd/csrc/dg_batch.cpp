@@ -80,6 +80,15 @@ struct dg_batch {
     hipEvent_t done = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    // graphs replaced while launches of them may still be queued on the
+    // stream: destroyed once the event recorded after their last launch has
+    // completed
+    struct Retired {
+        hipGraphExec_t exec;
+        hipGraph_t graph;
+        hipEvent_t after;
+    };
+    std::vector<Retired> retired;
 };
 
 namespace {
@@ -91,12 +100,50 @@ int member_index(const dg_batch *b, const dg_solver *h)
     return -1;
 }
 
+// Destroy the retired graphs whose launches have all run (all of them when
+// wait is set: the caller has synchronized the stream).
+void reap_graphs(dg_batch *b, bool wait)
+{
+    size_t keep = 0;
+    for (size_t i = 0; i < b->retired.size(); ++i) {
+        dg_batch::Retired &r = b->retired[i];
+        const hipError_t q = wait ? hipSuccess : hipEventQuery(r.after);
+        if (q == hipSuccess) {
+            (void)hipGraphExecDestroy(r.exec);
+            if (r.graph) (void)hipGraphDestroy(r.graph);
+            (void)hipEventDestroy(r.after);
+        } else {
+            if (q != hipErrorNotReady) (void)hipGetLastError();
+            b->retired[keep++] = r;
+        }
+    }
+    b->retired.resize(keep);
+}
+
+// Stop using the captured tick graph. Launches of it may still be queued on
+// the batch stream, so it is retired behind an event rather than destroyed
+// (its kernel arguments must outlive those launches).
 void drop_graph(dg_batch *b)
 {
-    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->gexec) {
+        hipEvent_t ev = nullptr;
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess &&
+            hipEventRecord(ev, b->stream) == hipSuccess) {
+            b->retired.push_back({b->gexec, b->graph, ev});
+        } else {
+            // no event: wait for the stream, then the graph is free
+            (void)hipGetLastError();
+            if (ev) (void)hipEventDestroy(ev);
+            (void)hipStreamSynchronize(b->stream);
+            (void)hipGraphExecDestroy(b->gexec);
+            if (b->graph) (void)hipGraphDestroy(b->graph);
+        }
+    } else if (b->graph) {
+        (void)hipGraphDestroy(b->graph);
+    }
     b->gexec = nullptr;
     b->graph = nullptr;
+    reap_graphs(b, false);
 }
 
 // Group the active members by class and upload their stage descriptors.
@@ -307,6 +354,7 @@ int dg_batch_destroy(dg_batch *b)
     (void)hipStreamSynchronize(b->stream);
     for (Member &m : b->members) m.h->batch = nullptr;
     drop_graph(b);
+    reap_graphs(b, true);
     if (b->dbuf) (void)hipFree(b->dbuf);
     for (int i = 0; i < 2; ++i) {
         if (b->pin[i]) (void)hipHostFree(b->pin[i]);
