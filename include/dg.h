@@ -224,7 +224,9 @@ int dg_autotune(dg_solver *h, int rk, double dt, int trial_steps);
 
 /* The launch configuration in use: cfg[0] tile order (0 XCD-contiguous,
  * 1 plain), cfg[1] z-slab size (z-units visited together), cfg[2] 1-D
- * halo-bound divisor (steps per launch = capacity / (cfg[2] * stages)),
+ * halo-bound divisor (steps per launch at most capacity / (cfg[2] * stages),
+ * default 10; a mesh split into one chunk per CU lowers it further until
+ * the chunk and its halos fit),
  * cfg[3] 1 once autotuned, cfg[4] x-block width (x-tiles visited together;
  * the number of x-tiles by default), cfg[5] z-march length (3-D RK3/RK4: a
  * workgroup runs cfg[5] consecutive layers of one tile column bottom to top

@@ -200,13 +200,23 @@ StageParams stage_program(const dg_solver *h, int rk, int s, double dt, bool zma
     return p;
 }
 
-MsPlan ms_plan(const dg_solver *h, int rk)
+int device_cus(int device)
+{
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || n < 1) {
+        (void)hipGetLastError();
+        return 256;
+    }
+    return n;
+}
+
+MsPlan ms_plan(const dg_solver *h, int rk, int64_t tcap)
 {
     MsPlan pl;
     if (h->dim != 1 || (rk != DG_RK3 && rk != DG_RK4) || !ms_fn(h->prec, h->eq, h->N)) return pl;
     const int64_t cap = ms_capacity(h->prec, h->eq, h->N);
     const int64_t K = h->K[0];
-    const int stages = stage_count(rk);
+    const int64_t stages = stage_count(rk);
     if (K <= cap && K * h->n1 <= kMsWholeNodes) {
         pl.whole = 1;
         pl.smax = kMsWholeSteps;
@@ -214,7 +224,13 @@ MsPlan ms_plan(const dg_solver *h, int rk)
         pl.nwg = 1;
     } else {
         pl.smax = (int)std::max<int64_t>(1, cap / (int64_t(h->ms_div) * stages));
-        pl.T = cap - 2 * int64_t(stages) * pl.smax;
+        if (tcap > 0 && tcap + 2 * stages <= cap) {
+            // T = tcap; as many steps per launch as the bound and the halos allow
+            pl.T = tcap;
+            pl.smax = (int)std::max<int64_t>(1, std::min<int64_t>(pl.smax, (cap - tcap) / (2 * stages)));
+        } else {
+            pl.T = cap - 2 * stages * pl.smax;
+        }
         pl.nwg = (K + pl.T - 1) / pl.T;
         if (pl.T < 1 || pl.nwg > (int64_t(1) << 31)) return MsPlan();
     }
@@ -252,11 +268,27 @@ MsProgram ms_program(const dg_solver *h, int rk)
     return g;
 }
 
-MsSolve ms_solve(const dg_solver *h, int rk, double dt, const MsPlan &pl)
+MsSchedule ms_schedule(int64_t nsteps, int smax, bool even)
+{
+    MsSchedule s;
+    s.count = (nsteps + smax - 1) / smax;
+    if (even && (s.count & 1)) {
+        if (nsteps > s.count)
+            ++s.count;
+        else
+            s.copy = true;
+    }
+    s.base = s.count ? nsteps / s.count : 0;
+    s.extra = s.count ? nsteps % s.count : 0;
+    return s;
+}
+
+MsSolve ms_solve(const dg_solver *h, int rk, double dt, const MsPlan &pl, bool pingpong)
 {
     MsSolve m;
     std::memset(&m, 0, sizeof(m));
     m.U = h->U;
+    m.V = pingpong ? h->Ya : h->U;
     m.K = h->K[0];
     m.T = pl.T;
     m.whole = pl.whole;
@@ -435,17 +467,20 @@ int step_ms(dg_solver *h, int rk, double dt, int64_t nsteps, const MsPlan &pl)
 {
     MsLaunch L;
     std::memset(&L, 0, sizeof(L));
+    // one workgroup updates the state in place; several ping-pong between
+    // U and Ya and end in U
+    const bool pp = pl.nwg > 1;
     L.solves = nullptr;
     L.D = h->Dtab;
-    L.one = ms_solve(h, rk, dt, pl);
+    L.one = ms_solve(h, rk, dt, pl, pp);
     L.prog = ms_program(h, rk);
     L.nwg = (uint32_t)pl.nwg;
     const MsFn fn = ms_fn(h->prec, h->eq, h->N);
-    for (int64_t done = 0; done < nsteps;) {
-        const int s = (int)std::min<int64_t>(pl.smax, nsteps - done);
-        L.nsteps = s;
+    const MsSchedule sc = ms_schedule(nsteps, pl.smax, pp);
+    for (int64_t i = 0; i < sc.launches(); ++i) {
+        L.nsteps = sc.steps(i);
         DG_HIP(fn(L, h->stream), "multi-step kernel launch");
-        done += s;
+        L.flip ^= pp ? 1 : 0;
     }
     return DG_OK;
 }
@@ -539,7 +574,9 @@ int step_rk6(dg_solver *h, double dt)
 
 int enqueue_steps(dg_solver *h, int rk, double dt, int64_t nsteps)
 {
-    const MsPlan pl = ms_plan(h, rk);
+    // a chunk per CU: the steps of a launch then run in one round of
+    // workgroups (chunking never changes an element's arithmetic)
+    const MsPlan pl = ms_plan(h, rk, ms_spread(h->K[0], h->cus));
     if (pl.ok) return step_ms(h, rk, dt, nsteps, pl);
     for (int64_t s = 0; s < nsteps; ++s) {
         const int rc = rk == DG_RK6 ? step_rk6(h, dt) : step_rk34(h, rk, dt);
@@ -663,6 +700,7 @@ int dg_create_ex(int dim, int N, const int64_t *K, int equation, const double *p
     }
     e = hipGetDevice(&h->device);
     if (e != hipSuccess) { delete h; return hip_fail(e, "hipGetDevice"); }
+    h->cus = device_cus(h->device);
 
     if (hip_stream) {
         h->stream = static_cast<hipStream_t>(hip_stream);
@@ -925,7 +963,7 @@ int dg_autotune(dg_solver *h, int rk, double dt, int trial_steps)
     if (pl.ok) {
         if (!pl.whole) {
             std::vector<Cfg> st;
-            for (int dv : {3, 4, 6, 10, 16}) st.push_back({h->plain_order, dv, h->slab, h->xblk, h->zlen});
+            for (int dv : {6, 10, 16, 24, 40}) st.push_back({h->plain_order, dv, h->slab, h->xblk, h->zlen});
             stages.push_back(st);
         }
     } else if (h->dim == 3) {

@@ -28,6 +28,10 @@ namespace {
 // more than a few direct launches. 1-D classes are advanced by the
 // temporally blocked kernel, up to smax steps per launch.
 constexpr int64_t kGraphMinTicks = 4;
+// Groups run on up to kLanes streams at once: the batch stream and kLanes - 1
+// side streams forked from it and joined back within every run (the GPU has
+// four hardware queues per process).
+constexpr int kLanes = 4;
 
 struct Member {
     dg_solver *h;
@@ -47,6 +51,8 @@ struct Group {
     MsFn msfn = nullptr;
     MsProgram prog{};
     int smax = 0;
+    int64_t tcap = 0;              // owned elements per workgroup asked for (0: the plan's own)
+    bool pp = false;               // members ping-pong between U and Ya (some has several workgroups)
     bool buf = true;
     std::vector<int> idx;          // member indices
     uint32_t ntiles = 0;
@@ -54,6 +60,7 @@ struct Group {
     const void *D = nullptr;
     const uint32_t *ftab = nullptr;
     int64_t grid = 0;
+    int lane = 0;                  // stream the group's launches go to
 };
 
 }  // namespace
@@ -78,8 +85,12 @@ struct dg_batch {
     bool pin_used[2] = {false, false};
     int pin_slot = 0;
     hipEvent_t done = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
+    hipStream_t side[kLanes - 1] = {};
+    hipEvent_t fork = nullptr, join[kLanes - 1] = {};
+    int lanes = 1;                 // lanes the current groups use
+    // per lane, the captured tick of its stage-kernel groups
+    hipGraph_t graph[kLanes] = {};
+    hipGraphExec_t gexec[kLanes] = {};
     // graphs replaced while launches of them may still be queued on the
     // stream: destroyed once the event recorded after their last launch has
     // completed
@@ -120,30 +131,67 @@ void reap_graphs(dg_batch *b, bool wait)
     b->retired.resize(keep);
 }
 
-// Stop using the captured tick graph. Launches of it may still be queued on
-// the batch stream, so it is retired behind an event rather than destroyed
-// (its kernel arguments must outlive those launches).
+// Stop using the captured tick graphs. Launches of them may still be queued
+// (the side streams' work is joined into the batch stream), so they are
+// retired behind an event rather than destroyed (their kernel arguments must
+// outlive those launches).
 void drop_graph(dg_batch *b)
 {
-    if (b->gexec) {
-        hipEvent_t ev = nullptr;
-        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess &&
-            hipEventRecord(ev, b->stream) == hipSuccess) {
-            b->retired.push_back({b->gexec, b->graph, ev});
-        } else {
-            // no event: wait for the stream, then the graph is free
-            (void)hipGetLastError();
-            if (ev) (void)hipEventDestroy(ev);
-            (void)hipStreamSynchronize(b->stream);
-            (void)hipGraphExecDestroy(b->gexec);
-            if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (int k = 0; k < kLanes; ++k) {
+        if (b->gexec[k]) {
+            hipEvent_t ev = nullptr;
+            if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess &&
+                hipEventRecord(ev, b->stream) == hipSuccess) {
+                b->retired.push_back({b->gexec[k], b->graph[k], ev});
+            } else {
+                // no event: wait for the stream, then the graph is free
+                (void)hipGetLastError();
+                if (ev) (void)hipEventDestroy(ev);
+                (void)hipStreamSynchronize(b->stream);
+                (void)hipGraphExecDestroy(b->gexec[k]);
+                if (b->graph[k]) (void)hipGraphDestroy(b->graph[k]);
+            }
+        } else if (b->graph[k]) {
+            (void)hipGraphDestroy(b->graph[k]);
         }
-    } else if (b->graph) {
-        (void)hipGraphDestroy(b->graph);
+        b->gexec[k] = nullptr;
+        b->graph[k] = nullptr;
     }
-    b->gexec = nullptr;
-    b->graph = nullptr;
     reap_graphs(b, false);
+}
+
+hipStream_t lane_stream(const dg_batch *b, int k) { return k == 0 ? b->stream : b->side[k - 1]; }
+
+// Spread the groups over the lanes, largest estimated work first, each to the
+// least loaded lane; create the side streams and events on first use.
+int assign_lanes(dg_batch *b)
+{
+    const int ng = (int)b->groups.size();
+    std::vector<int> order(ng);
+    std::vector<double> cost(ng);
+    for (int i = 0; i < ng; ++i) {
+        const Group &g = b->groups[i];
+        order[i] = i;
+        // a multi-step launch advances up to smax steps, a stage launch one stage
+        cost[i] = (double)g.ntiles * (g.ms ? 2.0 * g.stages : (double)g.stages);
+    }
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    b->lanes = std::max(1, std::min(kLanes, ng));
+    double load[kLanes] = {};
+    for (int i : order) {
+        int best = 0;
+        for (int k = 1; k < b->lanes; ++k)
+            if (load[k] < load[best]) best = k;
+        b->groups[i].lane = best;
+        load[best] += cost[i];
+    }
+    for (int k = 1; k < b->lanes; ++k) {
+        if (!b->side[k - 1])
+            DG_HIP(hipStreamCreateWithFlags(&b->side[k - 1], hipStreamNonBlocking), "hipStreamCreate");
+        if (!b->join[k - 1]) DG_HIP(hipEventCreateWithFlags(&b->join[k - 1], hipEventDisableTiming), "hipEventCreate");
+    }
+    if (b->lanes > 1 && !b->fork) DG_HIP(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming), "hipEventCreate");
+    return DG_OK;
 }
 
 // Group the active members by class and upload their stage descriptors.
@@ -151,6 +199,7 @@ int rebuild(dg_batch *b)
 {
     drop_graph(b);
     b->groups.clear();
+    b->lanes = 1;
     std::map<std::tuple<int, int, int, int, int>, int> key;
     for (size_t i = 0; i < b->members.size(); ++i) {
         const Member &m = b->members[i];
@@ -186,14 +235,28 @@ int rebuild(dg_batch *b)
     size_t header = 0;
     for (Group &g : b->groups) {
         const size_t n = g.idx.size();
+        if (g.ms) {
+            // a group of chunked meshes with fewer workgroups than the GPU
+            // has CUs is cut into smaller chunks, about one per CU
+            int64_t wgs = 0, chunked = 0;
+            const int cus = b->members[g.idx[0]].h->cus;
+            for (int i : g.idx) {
+                const MsPlan pl = ms_plan(b->members[i].h, b->members[i].rk);
+                if (!pl.ok) return fail(DG_ENOTSUP, "no multi-step plan for a 1-D member");
+                wgs += pl.nwg;
+                if (!pl.whole) chunked += b->members[i].h->K[0];
+            }
+            g.tcap = (chunked > 0 && wgs < cus) ? ms_spread(chunked, cus) : 0;
+        }
         uint64_t tiles = 0;
         for (int i : g.idx) {
             const dg_solver *h = b->members[i].h;
             if (g.ms) {
-                const MsPlan pl = ms_plan(h, b->members[i].rk);
+                const MsPlan pl = ms_plan(h, b->members[i].rk, g.tcap);
                 if (!pl.ok) return fail(DG_ENOTSUP, "no multi-step plan for a 1-D member");
                 tiles += (uint64_t)pl.nwg;
                 g.smax = std::min(g.smax, pl.smax);
+                g.pp = g.pp || pl.nwg > 1;
                 continue;
             }
             tiles += (uint64_t)h->ntiles;
@@ -209,6 +272,8 @@ int rebuild(dg_batch *b)
         g.grid = std::min<int64_t>((int64_t)tiles, kMaxGrid);
     }
     if (header == 0) return DG_OK;
+    int rc = assign_lanes(b);
+    if (rc) return rc;
     size_t total = header;
     for (Group &g : b->groups) {
         g.off_solve = total;
@@ -240,8 +305,8 @@ int rebuild(dg_batch *b)
             const Member &m = b->members[g.idx[j]];
             base[j] = t0;
             if (g.ms) {
-                const MsPlan pl = ms_plan(m.h, m.rk);
-                reinterpret_cast<MsSolve *>(par)[j] = ms_solve(m.h, m.rk, m.dt, pl);
+                const MsPlan pl = ms_plan(m.h, m.rk, g.tcap);
+                reinterpret_cast<MsSolve *>(par)[j] = ms_solve(m.h, m.rk, m.dt, pl, g.pp);
                 t0 += (uint32_t)pl.nwg;
                 continue;
             }
@@ -279,13 +344,14 @@ int rebuild(dg_batch *b)
     return DG_OK;
 }
 
-int launch_tick(dg_batch *b)
+// One RK step of the stage-kernel groups on lane k, enqueued on stream st.
+int launch_tick(dg_batch *b, int k, hipStream_t st)
 {
     int smax = 0;
     for (const Group &g : b->groups) smax = std::max(smax, g.stages);
     for (int s = 0; s < smax; ++s)
         for (const Group &g : b->groups) {
-            if (g.ms || s >= g.stages) continue;
+            if (g.ms || g.lane != k || s >= g.stages) continue;
             const uint32_t n = (uint32_t)g.idx.size();
             BatchLaunch L;
             L.params = reinterpret_cast<const StageParams *>(b->dbuf + g.off_params) + (size_t)s * n;
@@ -297,7 +363,7 @@ int launch_tick(dg_batch *b)
             L.xq = g.ntiles / kXcds;
             L.xr = g.ntiles % kXcds;
             L.nsolves = n;
-            DG_HIP(g.fn(L, g.buf, g.nin[s], g.grid, b->stream), "batched stage kernel launch");
+            DG_HIP(g.fn(L, g.buf, g.nin[s], g.grid, st), "batched stage kernel launch");
         }
     return DG_OK;
 }
@@ -361,6 +427,11 @@ int dg_batch_destroy(dg_batch *b)
         if (b->pin_ev[i]) (void)hipEventDestroy(b->pin_ev[i]);
     }
     if (b->done) (void)hipEventDestroy(b->done);
+    for (int k = 0; k < kLanes - 1; ++k) {
+        if (b->side[k]) (void)hipStreamDestroy(b->side[k]);
+        if (b->join[k]) (void)hipEventDestroy(b->join[k]);
+    }
+    if (b->fork) (void)hipEventDestroy(b->fork);
     if (b->own_stream) (void)hipStreamDestroy(b->stream);
     delete b;
     return DG_OK;
@@ -426,12 +497,48 @@ int dg_batch_run(dg_batch *b, int64_t max_steps, int64_t *steps_done)
         if ((rc = rebuild(b))) return rc;
         b->dirty = false;
     }
-    bool ticked = false;
-    for (const Group &g : b->groups) {
-        if (!g.ms) {
-            ticked = true;
-            continue;
+    bool ticked[kLanes] = {};
+    for (const Group &g : b->groups)
+        if (!g.ms) ticked[g.lane] = true;
+    // capture the lanes' tick graphs before any work is forked
+    bool captured = false;
+    for (int k = 0; k < kLanes; ++k) captured = captured || b->gexec[k];
+    const bool graph = (b->flags & DG_BATCH_GRAPH) && (captured || steps >= kGraphMinTicks);
+    for (int k = 0; graph && k < b->lanes; ++k) {
+        if (!ticked[k] || b->gexec[k]) continue;
+        const hipStream_t st = lane_stream(b, k);
+        DG_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        rc = launch_tick(b, k, st);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(st, &g);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
         }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        b->graph[k] = g;
+        e = hipGraphInstantiate(&b->gexec[k], b->graph[k], nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            drop_graph(b);
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+    }
+    // fork: the side lanes start after everything enqueued on the batch stream
+    if (b->lanes > 1) {
+        DG_HIP(hipEventRecord(b->fork, b->stream), "hipEventRecord");
+        for (int k = 1; k < b->lanes; ++k) DG_HIP(hipStreamWaitEvent(b->side[k - 1], b->fork, 0), "hipStreamWaitEvent");
+    }
+    // join: the batch stream continues after every lane's work (also when a
+    // launch failed part way)
+    auto join = [&]() -> int {
+        for (int k = 1; k < b->lanes; ++k) {
+            DG_HIP(hipEventRecord(b->join[k - 1], b->side[k - 1]), "hipEventRecord");
+            DG_HIP(hipStreamWaitEvent(b->stream, b->join[k - 1], 0), "hipStreamWaitEvent");
+        }
+        return DG_OK;
+    };
+    for (const Group &g : b->groups) {
+        if (!g.ms) continue;
         MsLaunch L;
         std::memset(&L, 0, sizeof(L));
         L.solves = reinterpret_cast<const MsSolve *>(b->dbuf + g.off_params);
@@ -440,37 +547,34 @@ int dg_batch_run(dg_batch *b, int64_t max_steps, int64_t *steps_done)
         L.D = g.D;
         L.prog = g.prog;
         L.nwg = g.ntiles;
-        for (int64_t done = 0; done < steps;) {
-            L.nsteps = (int)std::min<int64_t>(g.smax, steps - done);
-            DG_HIP(g.msfn(L, b->stream), "batched multi-step kernel launch");
-            done += L.nsteps;
+        const MsSchedule sc = ms_schedule(steps, g.smax, g.pp);
+        for (int64_t i = 0; i < sc.launches(); ++i) {
+            L.nsteps = sc.steps(i);
+            const hipError_t e = g.msfn(L, lane_stream(b, g.lane));
+            if (e != hipSuccess) {
+                (void)join();
+                return hip_fail(e, "batched multi-step kernel launch");
+            }
+            L.flip ^= g.pp ? 1 : 0;
         }
     }
-    if (!ticked) {
-        // every group stepped by the multi-step kernel
-    } else if ((b->flags & DG_BATCH_GRAPH) && (b->gexec || steps >= kGraphMinTicks)) {
-        if (!b->gexec) {
-            DG_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-            rc = launch_tick(b);
-            hipGraph_t g = nullptr;
-            hipError_t e = hipStreamEndCapture(b->stream, &g);
+    for (int k = 0; k < b->lanes; ++k) {
+        if (!ticked[k]) continue;
+        const hipStream_t st = lane_stream(b, k);
+        for (int64_t t = 0; t < steps; ++t) {
+            if (graph) {
+                const hipError_t e = hipGraphLaunch(b->gexec[k], st);
+                rc = e == hipSuccess ? DG_OK : hip_fail(e, "hipGraphLaunch");
+            } else {
+                rc = launch_tick(b, k, st);
+            }
             if (rc) {
-                if (g) (void)hipGraphDestroy(g);
+                (void)join();
                 return rc;
             }
-            if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-            b->graph = g;
-            e = hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0);
-            if (e != hipSuccess) {
-                drop_graph(b);
-                return hip_fail(e, "hipGraphInstantiate");
-            }
         }
-        for (int64_t t = 0; t < steps; ++t) DG_HIP(hipGraphLaunch(b->gexec, b->stream), "hipGraphLaunch");
-    } else {
-        for (int64_t t = 0; t < steps; ++t)
-            if ((rc = launch_tick(b))) return rc;
     }
+    if ((rc = join())) return rc;
     for (Member &m : b->members)
         if (m.remaining > 0) {
             m.remaining -= steps;

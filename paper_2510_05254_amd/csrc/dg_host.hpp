@@ -75,7 +75,8 @@ struct dg_solver {
     // on it): tile order 0 XCD-contiguous / 1 plain; 1-D steps per launch
     // follow from the halo bound capacity / (ms_div * stages)
     int plain_order = 0;
-    int ms_div = 6;
+    int ms_div = 10;
+    int cus = 256;                  // compute units of the device
     int64_t zlen = 1;               // 3-D: layers per z-marching unit (1 = one layer per tile)
     int tuned = 0;
     dg_batch *batch = nullptr;      // batch this solver belongs to, if any
@@ -121,12 +122,14 @@ StageParams stage_program(const dg_solver *h, int rk, int s, double dt, bool zma
 
 // 1-D multi-step plan: whole mode (one workgroup holds the periodic mesh,
 // up to kMsWholeSteps steps per launch) when the mesh fits in one
-// workgroup's LDS with at most kMsWholeNodes nodes; otherwise chunked, with
-// at most smax steps per launch so the halo (stages * smax elements per
-// side) stays within capacity / ms_div (6 unless tuned), and T owned
-// elements per workgroup.
+// workgroup's LDS with at most kMsWholeNodes nodes; otherwise chunked, with T
+// owned elements per workgroup and at most smax steps per launch (the halo is
+// stages * smax elements per side, at most capacity / ms_div).
+// tcap > 0 asks for T = tcap (one round of workgroups over the GPU's CUs:
+// a chunk per CU), with smax lowered as far as the halos then need to fit;
+// a tcap that cannot fit is ignored.
 constexpr int kMsWholeSteps = 4096;
-constexpr int64_t kMsWholeNodes = 2048;
+constexpr int64_t kMsWholeNodes = 512;
 struct MsPlan {
     bool ok = false;
     int whole = 0;
@@ -134,10 +137,28 @@ struct MsPlan {
     int64_t T = 0;
     int64_t nwg = 0;
 };
-MsPlan ms_plan(const dg_solver *h, int rk);
+MsPlan ms_plan(const dg_solver *h, int rk, int64_t tcap = 0);
+// compute units of a device (256 if the runtime does not say)
+int device_cus(int device);
+// the owned elements per workgroup that spread `elements` over `cus` CUs
+inline int64_t ms_spread(int64_t elements, int cus) { return (elements + cus - 1) / cus; }
 // Stage program of scheme rk as array indices (0 U, 1 A, 2 Ya, 3 Yb).
 MsProgram ms_program(const dg_solver *h, int rk);
 // Per-solve multi-step parameters (coefficients for step dt).
-MsSolve ms_solve(const dg_solver *h, int rk, double dt, const MsPlan &pl);
+// pingpong: the solve's launches alternate between U and Ya (V = Ya), else
+// update U in place (V = U; only for a mesh held by one workgroup)
+MsSolve ms_solve(const dg_solver *h, int rk, double dt, const MsPlan &pl, bool pingpong);
+// Launches for nsteps steps at most smax per launch. With ping-pong arrays
+// (even) the count is made even so that the state ends in U: the steps are
+// spread evenly over one more launch, or, when every launch already runs a
+// single step, a final copy launch (0 steps) is added.
+struct MsSchedule {
+    int64_t count = 0;               // launches that step
+    int64_t base = 0, extra = 0;     // launch i runs base + (i < extra) steps
+    bool copy = false;               // a trailing 0-step launch
+    int64_t launches() const { return count + (copy ? 1 : 0); }
+    int steps(int64_t i) const { return i < count ? int(base + (i < extra ? 1 : 0)) : 0; }
+};
+MsSchedule ms_schedule(int64_t nsteps, int smax, bool even);
 
 }  // namespace dg

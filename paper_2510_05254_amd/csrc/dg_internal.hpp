@@ -123,7 +123,12 @@ struct MsProgram {
 };
 
 struct MsSolve {
-    void *U;               // state, canonical layout (read first, written last)
+    // The state, canonical layout, in two arrays: a launch reads one and
+    // writes the other (MsLaunch::flip), so no workgroup reads a halo that a
+    // neighbouring chunk has already advanced; V == U for a mesh held by one
+    // workgroup, which reads everything before it writes.
+    void *U;
+    void *V;
     int64_t K;             // elements
     int64_t T;             // owned elements per workgroup (chunked mode)
     int whole;             // 1: one workgroup holds the whole periodic mesh
@@ -141,7 +146,8 @@ struct MsLaunch {
     MsSolve one;
     MsProgram prog;
     uint32_t nwg;              // workgroups
-    int nsteps;                // steps per launch (halo = stages * nsteps)
+    int nsteps;                // steps per launch (halo = stages * nsteps); 0: copy
+    int flip;                  // 0: read U, write V; 1: read V, write U
 };
 
 typedef hipError_t (*MsFn)(const MsLaunch &l, hipStream_t s);

@@ -10,9 +10,13 @@
 //
 // What differs is where the arrays live. A workgroup keeps its elements'
 // four RK arrays in LDS and runs all stages of `nsteps` steps there, with one
-// barrier per stage, so HBM sees one read and one write of U per launch
-// instead of 3.5 array passes per stage, and the step loop issues one launch
-// per `nsteps` steps instead of one per stage.
+// barrier per stage (two for Euler, whose nodal fluxes are staged in LDS
+// first), so HBM sees one read and one write of U per launch instead of 3.5
+// array passes per stage, and the step loop issues one launch per `nsteps`
+// steps instead of one per stage. One thread owns one node (and keeps row i
+// of D in registers); a workgroup of 1024 (or 512) threads covers
+// 1024 / (N+1) elements per pass, so even a small mesh has N+1 times more
+// threads in flight than elements.
 //   whole mode:   the workgroup holds the entire periodic mesh; neighbours
 //                 wrap inside LDS; any number of steps per launch.
 //   chunked mode: the workgroup owns T consecutive elements and loads a halo
@@ -36,14 +40,23 @@ template <typename real, int N, int EQ>
 struct Geo1 {
     static constexpr int N1 = N + 1;
     static constexpr int NV = EQ == 0 ? 1 : 2;
-    // one thread per element: an element's nodes sit at an odd stride S >= N+1
-    // (in doubles) so lanes reading element-strided LDS hit distinct banks
+    // an element's nodes sit at an odd stride S >= N+1 (in reals) so that
+    // lanes reading one node of consecutive elements hit distinct banks
     static constexpr int S = (N1 % 2) ? N1 : N1 + 1;
-    static constexpr int PER_ELEM = 4 * NV * S * (int)sizeof(real);    // U, A, Ya, Yb
-    static constexpr int BUDGET = 80 * 1024 - N1 * N1 * (int)sizeof(real);
-    // elements held (a multiple of 64); threads take one element per pass
-    static constexpr int CAP_E = ((BUDGET / PER_ELEM) / 64) * 64;
-    static constexpr int THREADS = CAP_E < 256 ? CAP_E : 256;
+    // U, A, Ya, Yb, and for Euler the nodal fluxes of the stage input
+    static constexpr int NARR = EQ == 0 ? 4 : 5;
+    static constexpr int PER_ELEM = NARR * NV * S * (int)sizeof(real);
+    // elements held: two workgroups share a CU's 160 KiB of LDS (512 bytes
+    // stay for the stage programs)
+    static constexpr int CAP_E = (80 * 1024 - 512) / PER_ELEM;
+    // 1024 threads in at most 64 VGPRs (two workgroups, eight waves per SIMD)
+    // where the kernel fits in them without spilling, else 512 threads in at
+    // most 128 VGPRs; a multiple of N+1, so a thread keeps its node on every
+    // pass
+    static constexpr bool BIG = sizeof(real) == 4 ? (EQ == 0 || N <= 6) : (EQ == 0 && N <= 7);
+    static constexpr int WAVES = BIG ? 8 : 4;
+    static constexpr int THREADS = N1 * ((BIG ? 1024 : 512) / N1);
+    static constexpr int EPP = THREADS / N1;                           // elements per pass
 };
 
 __device__ __forceinline__ double rcp_nr(double x)
@@ -59,6 +72,22 @@ __device__ __forceinline__ float rcp_nr(float x)
     float r = __builtin_amdgcn_rcpf(x);
     float e = __builtin_fmaf(-x, r, 1.0f);
     return __builtin_fmaf(r, e, r);
+}
+
+// A value that is the same in every lane, moved to scalar registers (the
+// per-solve constants are read through a generic pointer, which would
+// otherwise hold them in vector registers).
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ float uni(float x)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
+}
+__device__ __forceinline__ double uni(double x)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
+    return __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
 }
 
 // physical flux and wave speed of a 1-D state (advection: a u; isothermal
@@ -90,22 +119,26 @@ __device__ __forceinline__ void lf_flux(const real *UL, const real *FL, real lam
 }
 
 template <typename real, int N, int EQ>
-__global__ void __launch_bounds__((Geo1<real, N, EQ>::THREADS)) ms1_kernel(const MsLaunch l)
+__global__ void __launch_bounds__((Geo1<real, N, EQ>::THREADS)) __attribute__((amdgpu_waves_per_eu(Geo1<real, N, EQ>::WAVES)))
+ms1_kernel(const MsLaunch l)
 {
     using G = Geo1<real, N, EQ>;
     constexpr int N1 = G::N1, NV = G::NV, S = G::S, CAP_E = G::CAP_E, THREADS = G::THREADS;
+    constexpr int EPP = G::EPP;
     constexpr real INVW0 = real(N * (N + 1)) / real(2);    // 1/w_0 = 1/w_N
     __shared__ real sA[4][NV][CAP_E * S];                   // U, A, Ya, Yb
-    __shared__ real sD[N1 * N1];
+    __shared__ real sF[EQ == 0 ? 1 : NV][EQ == 0 ? 1 : CAP_E * S];
 
     const int tid = threadIdx.x;
+    const int i = tid % N1, e0 = tid / N1;                  // this thread's node, first element
     uint32_t s = 0, chunk = blockIdx.x;
     if (l.solves) {
         s = l.wg_solve[blockIdx.x];
         chunk = blockIdx.x - l.wg_base[s];
     }
     const MsSolve *P = l.solves ? l.solves + s : &l.one;
-    real *U = static_cast<real *>(P->U);
+    const real *Uin = static_cast<const real *>(l.flip ? P->V : P->U);
+    real *Uout = static_cast<real *>(l.flip ? P->U : P->V);
     const int64_t K = P->K;
     const bool whole = P->whole != 0;
     const int stages = l.prog.stages;
@@ -114,109 +147,124 @@ __global__ void __launch_bounds__((Geo1<real, N, EQ>::THREADS)) ms1_kernel(const
     const int town = int(whole ? K : (K - own0 < P->T ? K - own0 : P->T));
     const int L = town + 2 * H;                             // local elements
     const int64_t gfirst = own0 - H;                        // global element of local 0
-    const real par = real(P->par), rdx2 = real(P->rdx2);
+    const real par = uni(real(P->par)), rdx2 = uni(real(P->rdx2));
     const real sl = rdx2 * INVW0;
 
-    if (tid < N1 * N1) sD[tid] = static_cast<const real *>(l.D)[tid];
+    // the stage programs and coefficients, read once (stages read them from
+    // LDS instead of through the solve pointer)
+    __shared__ real sC[4][2][4];
+    __shared__ int8_t sG[4][8];
+    if (tid < 32) sC[tid >> 3][(tid >> 2) & 1][tid & 3] = real(P->coef[tid >> 3][(tid >> 2) & 1][tid & 3]);
+    if (tid >= 64 && tid < 96) {
+        const int st = (tid - 64) >> 3, k = tid & 7;
+        const MsProgram &g = l.prog;
+        sG[st][k] = k == 0 ? g.yin[st] : k == 1 ? g.nin[st] : k == 2 ? g.in0[st] : k == 3 ? g.in1[st]
+                  : k == 4 ? g.nout[st] : k == 5 ? g.out[st][0] : k == 6 ? g.out[st][1] : 0;
+    }
+    real d[N1];                                             // row i of D
+#pragma unroll
+    for (int m = 0; m < N1; ++m) d[m] = static_cast<const real *>(l.D)[i * N1 + m];
     // ---- load U over the local range (node-parallel, coalesced; periodic
     // wrap by one period at most)
     for (int idx = tid; idx < L * N1; idx += THREADS) {
-        const int le = idx / N1, i = idx - le * N1;
+        const int le = idx / N1, n = idx - le * N1;
         int64_t ge = gfirst + le;
         if (ge < 0) ge += K;
         if (ge >= K) ge -= K;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) sA[0][v][le * S + i] = U[(ge * NV + v) * N1 + i];
+        for (int v = 0; v < NV; ++v) sA[0][v][le * S + n] = Uin[(ge * NV + v) * N1 + n];
     }
     __syncthreads();
 
     int a = 0, b = L;          // elements on which the current stage input is valid
     for (int step = 0; step < l.nsteps; ++step) {
         for (int st = 0; st < stages; ++st) {
-            const int yi = l.prog.yin[st], nin = l.prog.nin[st], nout = l.prog.nout[st];
-            const int i0 = l.prog.in0[st], i1 = l.prog.in1[st];
+            const int yi = uni(int(sG[st][0])), nin = uni(int(sG[st][1])), nout = uni(int(sG[st][4]));
+            const int i0 = uni(int(sG[st][2])), i1 = uni(int(sG[st][3]));
             const int lo = whole ? 0 : a + 1, hi = whole ? L : b - 1;
             real cy[2], c0[2], c1[2], cr[2];
             int oi[2];
 #pragma unroll
             for (int o = 0; o < 2; ++o) {
-                cy[o] = real(P->coef[st][o][0]);
-                c0[o] = real(P->coef[st][o][1]);
-                c1[o] = real(P->coef[st][o][2]);
-                cr[o] = real(P->coef[st][o][3]);
-                oi[o] = l.prog.out[st][o];
+                cy[o] = uni(sC[st][o][0]);
+                c0[o] = uni(sC[st][o][1]);
+                c1[o] = uni(sC[st][o][2]);
+                cr[o] = uni(sC[st][o][3]);
+                oi[o] = uni(int(sG[st][5 + o]));
             }
-            for (int le = lo + tid; le < hi; le += THREADS) {
+            if constexpr (EQ != 0) {
+                // nodal fluxes of the stage input
+                for (int le = lo + e0; le < hi; le += EPP) {
+                    real u[NV], F[NV], lam;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) u[v] = sA[yi][v][le * S + i];
+                    flux1<real, EQ>(u, par, F, lam);
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) sF[v][le * S + i] = F[v];
+                }
+                __syncthreads();
+            }
+            for (int le = lo + e0; le < hi; le += EPP) {
                 const int base = le * S;
-                // the element's stage input and fluxes, in registers
-                real u[N1][NV], F[N1][NV], lam0, lamN;
+                // volume term at node i: -(2/dx) sum_m D_im F(U_m)
+                real acc[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) acc[v] = real(0);
 #pragma unroll
                 for (int m = 0; m < N1; ++m) {
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) u[m][v] = sA[yi][v][base + m];
-                    real lam;
-                    flux1<real, EQ>(u[m], par, F[m], lam);
-                    if (m == 0) lam0 = lam;
-                    if (m == N) lamN = lam;
+                    for (int v = 0; v < NV; ++v) acc[v] += d[m] * (EQ == 0 ? sA[yi][v][base + m] : sF[v][base + m]);
                 }
-                // volume term
-                real R[N1][NV];
+                real R[NV], u[NV];
 #pragma unroll
-                for (int i = 0; i < N1; ++i) {
-                    real acc[NV];
+                for (int v = 0; v < NV; ++v) {
+                    R[v] = real(0);
+                    u[v] = sA[yi][v][base + i];
+                }
+                if constexpr (EQ == 0) {
+                    R[0] -= rdx2 * (par * acc[0]);
+                } else {
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) acc[v] = real(0);
+                    for (int v = 0; v < NV; ++v) R[v] -= rdx2 * acc[v];
+                }
+                // node 0: the lower face (with element le-1); node N: the upper
+                // face (with le+1). Each face is evaluated by both elements
+                // from the same (lower, upper) pair.
+                if (i == 0 || i == N) {
+                    real F[NV], lam, Un[NV], Fn[NV], lamn, Fh[NV];
+                    flux1<real, EQ>(u, par, F, lam);
+                    if (i == 0) {
+                        const int ln = le == 0 ? L - 1 : le - 1;       // chunked: le >= 1
 #pragma unroll
-                    for (int m = 0; m < N1; ++m) {
-                        const real dm = sD[i * N1 + m];
+                        for (int v = 0; v < NV; ++v) Un[v] = sA[yi][v][ln * S + N];
+                        flux1<real, EQ>(Un, par, Fn, lamn);
+                        lf_flux<real, NV>(Un, Fn, lamn, u, F, lam, Fh);
 #pragma unroll
-                        for (int v = 0; v < NV; ++v) acc[v] += dm * (EQ == 0 ? u[m][v] : F[m][v]);
-                    }
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) R[i][v] = real(0);
-                    if constexpr (EQ == 0) {
-                        R[i][0] -= rdx2 * (par * acc[0]);
+                        for (int v = 0; v < NV; ++v) R[v] += sl * (Fh[v] - F[v]);
                     } else {
+                        const int un = le == L - 1 ? 0 : le + 1;       // chunked: le <= L-2
 #pragma unroll
-                        for (int v = 0; v < NV; ++v) R[i][v] -= rdx2 * acc[v];
+                        for (int v = 0; v < NV; ++v) Un[v] = sA[yi][v][un * S];
+                        flux1<real, EQ>(Un, par, Fn, lamn);
+                        lf_flux<real, NV>(u, F, lam, Un, Fn, lamn, Fh);
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) R[v] += -sl * (Fh[v] - F[v]);
                     }
                 }
-                // lower face (with element le-1) and upper face (with le+1);
-                // each face is evaluated by both elements from the same
-                // (lower, upper) pair
-                {
-                    const int ln = le == 0 ? L - 1 : le - 1;       // chunked: le >= 1
-                    const int un = le == L - 1 ? 0 : le + 1;       // chunked: le <= L-2
-                    real Un[NV], Fn[NV], lamn, Fh[NV];
+                // RK stage combination at node i (the outputs never alias the
+                // stage input; an output that is also an input is this node's)
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) Un[v] = sA[yi][v][ln * S + N];
-                    flux1<real, EQ>(Un, par, Fn, lamn);
-                    lf_flux<real, NV>(Un, Fn, lamn, u[0], F[0], lam0, Fh);
+                for (int v = 0; v < NV; ++v) {
+                    const real a0 = nin > 0 ? sA[i0][v][base + i] : real(0);
+                    const real a1 = nin > 1 ? sA[i1][v][base + i] : real(0);
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) R[0][v] += sl * (Fh[v] - F[0][v]);
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) Un[v] = sA[yi][v][un * S];
-                    flux1<real, EQ>(Un, par, Fn, lamn);
-                    lf_flux<real, NV>(u[N], F[N], lamN, Un, Fn, lamn, Fh);
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) R[N][v] += -sl * (Fh[v] - F[N][v]);
-                }
-                // RK stage combination
-#pragma unroll
-                for (int i = 0; i < N1; ++i) {
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) {
-                        const real a0 = nin > 0 ? sA[i0][v][base + i] : real(0);
-                        const real a1 = nin > 1 ? sA[i1][v][base + i] : real(0);
-#pragma unroll
-                        for (int o = 0; o < 2; ++o) {
-                            if (o < nout) {
-                                real val = cy[o] * u[i][v];
-                                if (nin > 0) val += c0[o] * a0;
-                                if (nin > 1) val += c1[o] * a1;
-                                val += cr[o] * R[i][v];
-                                sA[oi[o]][v][base + i] = val;
-                            }
+                    for (int o = 0; o < 2; ++o) {
+                        if (o < nout) {
+                            real val = cy[o] * u[v];
+                            if (nin > 0) val += c0[o] * a0;
+                            if (nin > 1) val += c1[o] * a1;
+                            val += cr[o] * R[v];
+                            sA[oi[o]][v][base + i] = val;
                         }
                     }
                 }
@@ -230,10 +278,10 @@ __global__ void __launch_bounds__((Geo1<real, N, EQ>::THREADS)) ms1_kernel(const
     }
     // ---- write back the owned elements
     for (int idx = H * N1 + tid; idx < (H + town) * N1; idx += THREADS) {
-        const int le = idx / N1, i = idx - le * N1;
+        const int le = idx / N1, n = idx - le * N1;
         const int64_t ge = gfirst + le;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) U[(ge * NV + v) * N1 + i] = sA[0][v][le * S + i];
+        for (int v = 0; v < NV; ++v) Uout[(ge * NV + v) * N1 + n] = sA[0][v][le * S + n];
     }
 }
 

@@ -96,6 +96,7 @@ extern "C" int dg_step_static(int dim, int N, const int64_t *K, int equation, co
     hipError_t e = hipGetDevice(&h.device);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     if (h.device < 0 || h.device >= kMaxDevices) return fail(DG_EDEVICE, "device ordinal out of range");
+    h.cus = device_cus(h.device);
     h.stream = static_cast<hipStream_t>(hip_stream);
 
     std::lock_guard<std::mutex> lock(g_mu);

@@ -83,6 +83,32 @@ def test_parity_1d_chunked_multistep(N, K, eq, rk, nsteps):
     assert np.all(np.abs(m1 - m0) <= 1e-14 * np.maximum(scale, 1.0))
 
 
+# Chunked meshes are cut into about one chunk per CU, so small meshes run as
+# many workgroups that each own a few elements and carry halos several times
+# wider. Launches read one state array and write the other, so a workgroup
+# never loads a halo that a neighbouring chunk has already advanced: every
+# steps-per-launch bound (and odd or even launch counts, single-step launches
+# ending in a copy launch) ends bitwise at the same state, equal to the oracle.
+@pytest.mark.parametrize("N,K,eq,nsteps", [(3, 700, ADV, 25), (7, 300, ADV, 13), (2, 2000, EUL, 9), (5, 129, ADV, 1)])
+def test_1d_chunkings_bitwise(N, K, eq, nsteps):
+    w, ax, U0, dt = case(1, N, (K,), eq, 31)
+    ref = None
+    with dg.Solver(1, N, (K,), eq, params(1, eq)) as s:
+        base = s.launch_config()
+        for div in (10, 6, 24, 40, 1024):
+            c = list(base)
+            c[2] = div
+            s.set_launch_config(c)
+            s.set_state(U0)
+            s.step(4, dt, nsteps)
+            got = s.get_state()
+            if ref is None:
+                ref = got
+            np.testing.assert_array_equal(got, ref, err_msg=f"halo divisor {div}")
+    Uo = oracle.step(1, N, (K,), eq, params(1, eq), U0, 4, dt, nsteps)
+    parity(ref, Uo, what=f"1-D N={N} K={K} eq={eq} chunked")
+
+
 def test_parity_1d_whole_mesh_many_steps():
     """A mesh held by one workgroup, stepped past the per-launch step limit.
     Over 4100 steps the N = 1 solution decays by about 1e5, so rounding is
