@@ -35,6 +35,11 @@ first at saturation (every request arrives at time 0) for the capacity C in
 solves/s, then with Poisson arrivals at each rate multiple of C; each run is
 repeated one solve at a time (FIFO, dg_step alone) on the same GPU. Prints one
 JSON line with solves/s and p50/p99 latency (completion - arrival) per run.
+The default time scale 0.01 shortens every final time 100-fold so the run
+takes minutes; the output then names the workload ..._final_times_x0.01 and
+says REDUCED in config.final_times. --time-scale 1 runs the stated final times
+(the 2000 requests then take about 2.3e8 RK4 steps in all, mostly long 1-D
+solves: tens of minutes).
 
 --efficiency repeats the paper's error-versus-computing-time study (Sec. 3.1):
 2-D advection with a = (1, 0) over one revolution (T = 1) from
@@ -178,14 +183,14 @@ def serve_main(a):
 
     def run_batched(rate, seed):
         with serve.Server(arena, chunk=a.chunk, graph=not a.no_graph) as srv:
-            done, rej, wall = srv.serve(serve.with_rate(reqs, rate, seed), prep)
+            done, rej, wall = srv.serve(serve.with_rate(reqs, rate, seed), prep, log=log)
         out = serve.summarize(done, wall)
         out["rejected"] = len(rej)
         log(f"batched rate={rate:.4g}: {json.dumps(out)}")
         return out
 
     def run_seq(rate, seed):
-        done, rej, wall = serve.serve_sequential(serve.with_rate(reqs, rate, seed), prep, arena)
+        done, rej, wall = serve.serve_sequential(serve.with_rate(reqs, rate, seed), prep, arena, log=log)
         out = serve.summarize(done, wall)
         out["rejected"] = len(rej)
         log(f"sequential rate={rate:.4g}: {json.dumps(out)}")
@@ -208,8 +213,12 @@ def serve_main(a):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"served_stream_{a.requests}req_timescale{a.time_scale:g}",
-                   "requests": a.requests, "time_scale": a.time_scale, "rk": 4,
+        "config": {"workload": f"served_stream_{a.requests}req" +
+                               ("" if a.time_scale == 1 else f"_final_times_x{a.time_scale:g}"),
+                   "requests": a.requests, "time_scale": a.time_scale,
+                   "final_times": ("as stated, uniform in [0.1, 1]" if a.time_scale == 1 else
+                                   f"REDUCED: uniform in [0.1, 1] x {a.time_scale:g}"),
+                   "rk": 4,
                    "arena_gib": a.arena_gib, "chunk": a.chunk, "graph": not a.no_graph,
                    "dof_updates": upd},
         "capacity": {"batched": cap_b, "sequential": cap_s,

@@ -213,7 +213,9 @@ int device_cus(int device)
 MsPlan ms_plan(const dg_solver *h, int rk, int64_t tcap)
 {
     MsPlan pl;
-    if (h->dim != 1 || (rk != DG_RK3 && rk != DG_RK4) || !ms_fn(h->prec, h->eq, h->N)) return pl;
+    if (h->dim != 1 || (rk != DG_RK3 && rk != DG_RK4) || !ms_fn(h->prec, h->eq, h->N) ||
+        !ms_program_matches(ms_program(h, rk), rk))
+        return pl;
     const int64_t cap = ms_capacity(h->prec, h->eq, h->N);
     const int64_t K = h->K[0];
     const int64_t stages = stage_count(rk);
@@ -259,13 +261,21 @@ MsProgram ms_program(const dg_solver *h, int rk)
         g.out[st][0] = index(p.out0);
         g.out[st][1] = p.nout > 1 ? index(p.out1) : 0;
     }
-    // the output each stage hands to the next one (the last stage's U starts
-    // the next step)
-    for (int st = 0; st < g.stages; ++st) {
-        const int8_t want = st + 1 < g.stages ? g.yin[st + 1] : g.yin[0];
-        g.next[st] = g.out[st][0] == want ? 0 : 1;
-    }
     return g;
+}
+
+bool ms_program_matches(const MsProgram &g, int rk)
+{
+    const MsProgram &t = rk == DG_RK4 ? kMsProgRk4 : kMsProgRk3;
+    if (g.stages != t.stages) return false;
+    for (int st = 0; st < t.stages; ++st) {
+        if (g.yin[st] != t.yin[st] || g.nin[st] != t.nin[st] || g.nout[st] != t.nout[st]) return false;
+        if (t.nin[st] > 0 && g.in0[st] != t.in0[st]) return false;
+        if (t.nin[st] > 1 && g.in1[st] != t.in1[st]) return false;
+        for (int o = 0; o < t.nout[st]; ++o)
+            if (g.out[st][o] != t.out[st][o]) return false;
+    }
+    return true;
 }
 
 MsSchedule ms_schedule(int64_t nsteps, int smax, bool even)
@@ -473,7 +483,7 @@ int step_ms(dg_solver *h, int rk, double dt, int64_t nsteps, const MsPlan &pl)
     L.solves = nullptr;
     L.D = h->Dtab;
     L.one = ms_solve(h, rk, dt, pl, pp);
-    L.prog = ms_program(h, rk);
+    L.rk = rk;
     L.nwg = (uint32_t)pl.nwg;
     const MsFn fn = ms_fn(h->prec, h->eq, h->N);
     const MsSchedule sc = ms_schedule(nsteps, pl.smax, pp);

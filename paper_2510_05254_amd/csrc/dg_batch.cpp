@@ -49,7 +49,6 @@ struct Group {
     // per launch
     bool ms = false;
     MsFn msfn = nullptr;
-    MsProgram prog{};
     int smax = 0;
     int64_t tcap = 0;              // owned elements per workgroup asked for (0: the plan's own)
     bool pp = false;               // members ping-pong between U and Ya (some has several workgroups)
@@ -217,7 +216,6 @@ int rebuild(dg_batch *b)
             if (ms_plan(h, m.rk).ok) {
                 g.ms = true;
                 g.msfn = ms_fn(h->prec, h->eq, h->N);
-                g.prog = ms_program(h, m.rk);
                 g.smax = kMsWholeSteps;
             }
             g.D = h->Dtab;
@@ -545,7 +543,7 @@ int dg_batch_run(dg_batch *b, int64_t max_steps, int64_t *steps_done)
         L.wg_solve = reinterpret_cast<const uint32_t *>(b->dbuf + g.off_solve);
         L.wg_base = reinterpret_cast<const uint32_t *>(b->dbuf + g.off_base);
         L.D = g.D;
-        L.prog = g.prog;
+        L.rk = g.rk;
         L.nwg = g.ntiles;
         const MsSchedule sc = ms_schedule(steps, g.smax, g.pp);
         for (int64_t i = 0; i < sc.launches(); ++i) {

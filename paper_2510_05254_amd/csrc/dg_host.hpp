@@ -144,6 +144,8 @@ int device_cus(int device);
 inline int64_t ms_spread(int64_t elements, int cus) { return (elements + cus - 1) / cus; }
 // Stage program of scheme rk as array indices (0 U, 1 A, 2 Ya, 3 Yb).
 MsProgram ms_program(const dg_solver *h, int rk);
+// whether a stage program is the multi-step kernel's kMsProgRk3/kMsProgRk4
+bool ms_program_matches(const MsProgram &g, int rk);
 // Per-solve multi-step parameters (coefficients for step dt).
 // pingpong: the solve's launches alternate between U and Ya (V = Ya), else
 // update U in place (V = U; only for a mesh held by one workgroup)

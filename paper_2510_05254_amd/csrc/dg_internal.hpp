@@ -119,8 +119,14 @@ struct LayoutParams {
 struct MsProgram {
     int stages;
     int8_t yin[4], nin[4], in0[4], in1[4], nout[4], out[4][2];
-    int8_t next[4];        // output (0/1) that is the next stage's input
 };
+// The fused stage programs of the RK3 and RK4 schedules in those indices.
+// The multi-step kernel takes them at compile time; the host uses that kernel
+// only while its own stage programs equal these.
+constexpr MsProgram kMsProgRk3 = {3, {0, 2, 3, 0}, {0, 1, 1, 0}, {0, 0, 1, 0}, {0, 0, 0, 0}, {2, 1, 1, 0},
+                                  {{2, 1}, {3, 0}, {0, 0}, {0, 0}}};
+constexpr MsProgram kMsProgRk4 = {4, {0, 3, 2, 3}, {0, 1, 2, 1}, {0, 0, 0, 1}, {0, 0, 1, 0}, {1, 2, 2, 1},
+                                  {{3, 0}, {1, 2}, {1, 3}, {0, 0}}};
 
 struct MsSolve {
     // The state, canonical layout, in two arrays: a launch reads one and
@@ -144,7 +150,7 @@ struct MsLaunch {
     const uint32_t *wg_base;   // batched: first workgroup of each solve
     const void *D;             // (N+1)^2 differentiation matrix (state precision)
     MsSolve one;
-    MsProgram prog;
+    int rk;                    // 3 or 4: the stage program kMsProgRk3 / kMsProgRk4
     uint32_t nwg;              // workgroups
     int nsteps;                // steps per launch (halo = stages * nsteps); 0: copy
     int flip;                  // 0: read U, write V; 1: read V, write U

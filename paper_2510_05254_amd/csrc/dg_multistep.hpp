@@ -9,14 +9,15 @@
 // cr R over the arrays U, A, Ya, Yb).
 //
 // What differs is where the arrays live. A workgroup keeps its elements'
-// four RK arrays in LDS and runs all stages of `nsteps` steps there, with one
-// barrier per stage (two for Euler, whose nodal fluxes are staged in LDS
-// first), so HBM sees one read and one write of U per launch instead of 3.5
-// array passes per stage, and the step loop issues one launch per `nsteps`
-// steps instead of one per stage. One thread owns one node (and keeps row i
-// of D in registers); a workgroup of 1024 (or 512) threads covers
-// 1024 / (N+1) elements per pass, so even a small mesh has N+1 times more
-// threads in flight than elements.
+// four RK arrays in LDS and runs all stages of `nsteps` steps there, in two
+// phases per stage (the face fluxes, once per face, and for Euler the nodal
+// fluxes; then every node), so HBM sees one read and one write of U per
+// launch instead of 3.5 array passes per stage, and the step loop issues one
+// launch per `nsteps` steps instead of one per stage. One thread owns one node
+// (and keeps row i of D in registers); a workgroup of 1024 (or 512) threads
+// covers 1024 / (N+1) elements per pass, so even a small mesh has N+1 times
+// more threads in flight than elements. The RK3 and RK4 stage programs are
+// compile-time constants (kMsProgRk3, kMsProgRk4).
 //   whole mode:   the workgroup holds the entire periodic mesh; neighbours
 //                 wrap inside LDS; any number of steps per launch.
 //   chunked mode: the workgroup owns T consecutive elements and loads a halo
@@ -26,9 +27,8 @@
 //                 stage; after nsteps steps exactly the owned elements are
 //                 valid and are written back. Halo work is redundant: every
 //                 copy of an element computes the same values.
-// Both sides of a face evaluate Fhat from the same (lower, upper) trace pair
-// with contraction off, so they get the same bits and the scheme conserves
-// to roundoff.
+// Each face's Fhat is evaluated once (contraction off) and lifted into both
+// of its elements, so the scheme conserves to roundoff.
 #pragma once
 
 #include "dg_internal.hpp"
@@ -43,11 +43,12 @@ struct Geo1 {
     // an element's nodes sit at an odd stride S >= N+1 (in reals) so that
     // lanes reading one node of consecutive elements hit distinct banks
     static constexpr int S = (N1 % 2) ? N1 : N1 + 1;
-    // U, A, Ya, Yb, and for Euler the nodal fluxes of the stage input
+    // U, A, Ya, Yb, and for Euler the nodal fluxes of the stage input; one
+    // face flux per element
     static constexpr int NARR = EQ == 0 ? 4 : 5;
-    static constexpr int PER_ELEM = NARR * NV * S * (int)sizeof(real);
+    static constexpr int PER_ELEM = NARR * NV * S * (int)sizeof(real) + NV * (int)sizeof(real);
     // elements held: two workgroups share a CU's 160 KiB of LDS (512 bytes
-    // stay for the stage programs)
+    // stay for the stage coefficients and the last face)
     static constexpr int CAP_E = (80 * 1024 - 512) / PER_ELEM;
     // 1024 threads in at most 64 VGPRs (two workgroups, eight waves per SIMD)
     // where the kernel fits in them without spilling, else 512 threads in at
@@ -77,7 +78,6 @@ __device__ __forceinline__ float rcp_nr(float x)
 // A value that is the same in every lane, moved to scalar registers (the
 // per-solve constants are read through a generic pointer, which would
 // otherwise hold them in vector registers).
-__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
 __device__ __forceinline__ float uni(float x)
 {
     return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
@@ -118,16 +118,19 @@ __device__ __forceinline__ void lf_flux(const real *UL, const real *FL, real lam
     for (int v = 0; v < NV; ++v) Fh[v] = real(0.5) * ((FL[v] + FR[v]) - alpha * (UR[v] - UL[v]));
 }
 
-template <typename real, int N, int EQ>
+template <typename real, int N, int EQ, int RK>
 __global__ void __launch_bounds__((Geo1<real, N, EQ>::THREADS)) __attribute__((amdgpu_waves_per_eu(Geo1<real, N, EQ>::WAVES)))
 ms1_kernel(const MsLaunch l)
 {
     using G = Geo1<real, N, EQ>;
     constexpr int N1 = G::N1, NV = G::NV, S = G::S, CAP_E = G::CAP_E, THREADS = G::THREADS;
     constexpr int EPP = G::EPP;
+    constexpr MsProgram PG = RK == 4 ? kMsProgRk4 : kMsProgRk3;
     constexpr real INVW0 = real(N * (N + 1)) / real(2);    // 1/w_0 = 1/w_N
     __shared__ real sA[4][NV][CAP_E * S];                   // U, A, Ya, Yb
     __shared__ real sF[EQ == 0 ? 1 : NV][EQ == 0 ? 1 : CAP_E * S];
+    __shared__ real sH[NV][CAP_E + 1];                      // Fhat of face f (elements f-1, f)
+    __shared__ real sC[4][2][4];                            // stage coefficients cy, c0, c1, cr
 
     const int tid = threadIdx.x;
     const int i = tid % N1, e0 = tid / N1;                  // this thread's node, first element
@@ -141,8 +144,7 @@ ms1_kernel(const MsLaunch l)
     real *Uout = static_cast<real *>(l.flip ? P->U : P->V);
     const int64_t K = P->K;
     const bool whole = P->whole != 0;
-    const int stages = l.prog.stages;
-    const int H = whole ? 0 : stages * l.nsteps;
+    const int H = whole ? 0 : PG.stages * l.nsteps;
     const int64_t own0 = whole ? 0 : int64_t(chunk) * P->T;
     const int town = int(whole ? K : (K - own0 < P->T ? K - own0 : P->T));
     const int L = town + 2 * H;                             // local elements
@@ -150,17 +152,8 @@ ms1_kernel(const MsLaunch l)
     const real par = uni(real(P->par)), rdx2 = uni(real(P->rdx2));
     const real sl = rdx2 * INVW0;
 
-    // the stage programs and coefficients, read once (stages read them from
-    // LDS instead of through the solve pointer)
-    __shared__ real sC[4][2][4];
-    __shared__ int8_t sG[4][8];
+    // the stage coefficients, read once
     if (tid < 32) sC[tid >> 3][(tid >> 2) & 1][tid & 3] = real(P->coef[tid >> 3][(tid >> 2) & 1][tid & 3]);
-    if (tid >= 64 && tid < 96) {
-        const int st = (tid - 64) >> 3, k = tid & 7;
-        const MsProgram &g = l.prog;
-        sG[st][k] = k == 0 ? g.yin[st] : k == 1 ? g.nin[st] : k == 2 ? g.in0[st] : k == 3 ? g.in1[st]
-                  : k == 4 ? g.nout[st] : k == 5 ? g.out[st][0] : k == 6 ? g.out[st][1] : 0;
-    }
     real d[N1];                                             // row i of D
 #pragma unroll
     for (int m = 0; m < N1; ++m) d[m] = static_cast<const real *>(l.D)[i * N1 + m];
@@ -178,22 +171,39 @@ ms1_kernel(const MsLaunch l)
 
     int a = 0, b = L;          // elements on which the current stage input is valid
     for (int step = 0; step < l.nsteps; ++step) {
-        for (int st = 0; st < stages; ++st) {
-            const int yi = uni(int(sG[st][0])), nin = uni(int(sG[st][1])), nout = uni(int(sG[st][4]));
-            const int i0 = uni(int(sG[st][2])), i1 = uni(int(sG[st][3]));
+#pragma unroll
+        for (int st = 0; st < PG.stages; ++st) {
+            const int yi = PG.yin[st], nin = PG.nin[st], nout = PG.nout[st];
+            const int i0 = PG.in0[st], i1 = PG.in1[st];
             const int lo = whole ? 0 : a + 1, hi = whole ? L : b - 1;
             real cy[2], c0[2], c1[2], cr[2];
-            int oi[2];
 #pragma unroll
             for (int o = 0; o < 2; ++o) {
                 cy[o] = uni(sC[st][o][0]);
                 c0[o] = uni(sC[st][o][1]);
                 c1[o] = uni(sC[st][o][2]);
                 cr[o] = uni(sC[st][o][3]);
-                oi[o] = uni(int(sG[st][5 + o]));
+            }
+            // ---- phase 1: eq. LF on every face the stage needs, once per face
+            // from its (lower, upper) pair (face f joins elements f-1 and f;
+            // whole mode: faces 0..L-1, face 0 wrapping to element L-1), and
+            // for Euler the nodal fluxes of the stage input
+            const int fhi = whole ? L - 1 : hi;
+            for (int f = lo + tid; f <= fhi; f += THREADS) {
+                const int el = f == 0 ? L - 1 : f - 1;
+                real UL[NV], UR[NV], FL[NV], FR[NV], lamL, lamR, Fh[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    UL[v] = sA[yi][v][el * S + N];
+                    UR[v] = sA[yi][v][f * S];
+                }
+                flux1<real, EQ>(UL, par, FL, lamL);
+                flux1<real, EQ>(UR, par, FR, lamR);
+                lf_flux<real, NV>(UL, FL, lamL, UR, FR, lamR, Fh);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) sH[v][f] = Fh[v];
             }
             if constexpr (EQ != 0) {
-                // nodal fluxes of the stage input
                 for (int le = lo + e0; le < hi; le += EPP) {
                     real u[NV], F[NV], lam;
 #pragma unroll
@@ -202,11 +212,12 @@ ms1_kernel(const MsLaunch l)
 #pragma unroll
                     for (int v = 0; v < NV; ++v) sF[v][le * S + i] = F[v];
                 }
-                __syncthreads();
             }
+            __syncthreads();
+            // ---- phase 2: node i of each element
             for (int le = lo + e0; le < hi; le += EPP) {
                 const int base = le * S;
-                // volume term at node i: -(2/dx) sum_m D_im F(U_m)
+                // volume term: -(2/dx) sum_m D_im F(U_m)
                 real acc[NV];
 #pragma unroll
                 for (int v = 0; v < NV; ++v) acc[v] = real(0);
@@ -227,28 +238,23 @@ ms1_kernel(const MsLaunch l)
 #pragma unroll
                     for (int v = 0; v < NV; ++v) R[v] -= rdx2 * acc[v];
                 }
-                // node 0: the lower face (with element le-1); node N: the upper
-                // face (with le+1). Each face is evaluated by both elements
-                // from the same (lower, upper) pair.
+                // lifts at the end nodes: +-(2/dx)(1/w_0)(Fhat - F)
                 if (i == 0 || i == N) {
-                    real F[NV], lam, Un[NV], Fn[NV], lamn, Fh[NV];
-                    flux1<real, EQ>(u, par, F, lam);
-                    if (i == 0) {
-                        const int ln = le == 0 ? L - 1 : le - 1;       // chunked: le >= 1
-#pragma unroll
-                        for (int v = 0; v < NV; ++v) Un[v] = sA[yi][v][ln * S + N];
-                        flux1<real, EQ>(Un, par, Fn, lamn);
-                        lf_flux<real, NV>(Un, Fn, lamn, u, F, lam, Fh);
-#pragma unroll
-                        for (int v = 0; v < NV; ++v) R[v] += sl * (Fh[v] - F[v]);
+                    real F[NV];
+                    if constexpr (EQ == 0) {
+                        real lam;
+                        flux1<real, EQ>(u, par, F, lam);
                     } else {
-                        const int un = le == L - 1 ? 0 : le + 1;       // chunked: le <= L-2
 #pragma unroll
-                        for (int v = 0; v < NV; ++v) Un[v] = sA[yi][v][un * S];
-                        flux1<real, EQ>(Un, par, Fn, lamn);
-                        lf_flux<real, NV>(u, F, lam, Un, Fn, lamn, Fh);
+                        for (int v = 0; v < NV; ++v) F[v] = sF[v][base + i];
+                    }
+                    if (i == 0) {
 #pragma unroll
-                        for (int v = 0; v < NV; ++v) R[v] += -sl * (Fh[v] - F[v]);
+                        for (int v = 0; v < NV; ++v) R[v] += sl * (sH[v][le] - F[v]);
+                    } else {
+                        const int fu = whole && le == L - 1 ? 0 : le + 1;
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) R[v] += -sl * (sH[v][fu] - F[v]);
                     }
                 }
                 // RK stage combination at node i (the outputs never alias the
@@ -264,7 +270,7 @@ ms1_kernel(const MsLaunch l)
                             if (nin > 0) val += c0[o] * a0;
                             if (nin > 1) val += c1[o] * a1;
                             val += cr[o] * R[v];
-                            sA[oi[o]][v][base + i] = val;
+                            sA[PG.out[st][o]][v][base + i] = val;
                         }
                     }
                 }
@@ -288,7 +294,10 @@ ms1_kernel(const MsLaunch l)
 template <typename real, int N, int EQ>
 hipError_t launch_ms1(const MsLaunch &l, hipStream_t s)
 {
-    hipLaunchKernelGGL((ms1_kernel<real, N, EQ>), dim3(l.nwg), dim3(Geo1<real, N, EQ>::THREADS), 0, s, l);
+    if (l.rk == 3)
+        hipLaunchKernelGGL((ms1_kernel<real, N, EQ, 3>), dim3(l.nwg), dim3(Geo1<real, N, EQ>::THREADS), 0, s, l);
+    else
+        hipLaunchKernelGGL((ms1_kernel<real, N, EQ, 4>), dim3(l.nwg), dim3(Geo1<real, N, EQ>::THREADS), 0, s, l);
     return hipGetLastError();
 }
 

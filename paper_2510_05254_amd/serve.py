@@ -238,9 +238,10 @@ class Server:
             out.append(r)
         return out
 
-    def serve(self, requests, prepared):
+    def serve(self, requests, prepared, log=None, log_every: float = 20.0):
         """Serve `requests` (any order; arrival times in seconds from the call).
-        prepared[rid] = (U0, dt, nsteps). Returns (completed, rejected, wall)."""
+        prepared[rid] = (U0, dt, nsteps). Returns (completed, rejected, wall).
+        log(msg), if given, gets a progress line every log_every seconds."""
         import torch
         from collections import deque
         pending = deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
@@ -249,8 +250,13 @@ class Server:
         done, rejected = [], []
         t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0          # noqa: E731
+        last = 0.0
         while pending or waiting or self.active:
             t = now()
+            if log and t - last >= log_every:
+                last = t
+                log(f"{t:.0f} s: {len(done)} done, {len(self.active)} active, {len(waiting)} waiting, "
+                    f"{len(pending)} not arrived")
             while pending and pending[0].arrival <= t:
                 waiting.append(pending.popleft())
             while waiting and len(self.active) < self.max_slots:
@@ -280,10 +286,11 @@ class Server:
         return done, rejected, now()
 
 
-def serve_sequential(requests, prepared, arena_bytes: int, keep_results: bool = False):
+def serve_sequential(requests, prepared, arena_bytes: int, keep_results: bool = False, log=None,
+                     log_every: float = 20.0):
     """Baseline on the same GPU: FIFO, one solve at a time, each stepped alone
     with dg_step on one stream from one arena (no per-request allocation).
-    Returns (completed, rejected, wall)."""
+    Returns (completed, rejected, wall). log as for Server.serve."""
     import torch
     stream = torch.cuda.Stream()
     arena = Arena(arena_bytes)
@@ -291,7 +298,11 @@ def serve_sequential(requests, prepared, arena_bytes: int, keep_results: bool = 
     order = sorted(requests, key=lambda r: (r.arrival, r.rid))
     t0 = time.perf_counter()
     now = lambda: time.perf_counter() - t0              # noqa: E731
+    last = 0.0
     for r in order:
+        if log and now() - last >= log_every:
+            last = now()
+            log(f"{last:.0f} s: {len(done)} of {len(order)} done")
         while now() < r.arrival:
             time.sleep(min(r.arrival - now(), 0.005))
         U0, r.dt, r.nsteps = prepared[r.rid]
