@@ -255,9 +255,12 @@ int dg_set_launch_config(dg_solver *h, const int64_t *cfg, int n);
  * A batch advances its member solvers on the batch's stream. Each "tick" is
  * one RK step of every active member; all members that share a kernel class
  * (precision, equation, dim, N) and scheme are advanced by one launch per RK
- * stage, whatever their meshes, arrays and time steps, so many small solves
- * fill the GPU together. Members keep their own state arrays; results are
- * bitwise those of dg_step on the same member alone.
+ * stage (1-D RK3/RK4: per launch of the temporally blocked kernel), whatever
+ * their meshes, arrays and time steps, so many small solves fill the GPU
+ * together; different classes run concurrently on up to four streams forked
+ * from the batch stream and joined back within every dg_batch_run. Members
+ * keep their own state arrays; results are bitwise those of dg_step on the
+ * same member alone.
  * ------------------------------------------------------------------------ */
 
 #define DG_BATCH_GRAPH 1   /* replay ticks from a captured hipGraph of one tick
@@ -273,10 +276,12 @@ int dg_batch_create(void *hip_stream, int flags, dg_batch **out);
 int dg_batch_destroy(dg_batch *b);
 
 /* Add solver h (state set, on the batch's device, not in another batch) to
- * run nsteps >= 1 more steps of scheme rk (DG_RK3 or DG_RK4; DG_ENOTSUP for
- * DG_RK6) with step dt > 0. While a member, h must not be stepped or have its
- * state set directly (DG_ESTATE); dg_get_state / dg_l2_error / dg_mass on it
- * are stream-ordered after the batch work enqueued so far. */
+ * run nsteps >= 1 more steps of scheme rk (DG_RK3, DG_RK4 or DG_RK6) with
+ * step dt > 0. RK6 members need the RK6 stage store as dg_step does (an
+ * external workspace of dg_workspace_bytes(..., DG_RK6), else DG_ENOMEM; a
+ * library-owned one allocates it here). While a member, h must not be stepped
+ * or have its state set directly (DG_ESTATE); dg_get_state / dg_l2_error /
+ * dg_mass on it are stream-ordered after the batch work enqueued so far. */
 int dg_batch_add(dg_batch *b, dg_solver *h, int rk, double dt, int64_t nsteps);
 
 /* Remove member h (finished or not); its remaining steps are dropped. */

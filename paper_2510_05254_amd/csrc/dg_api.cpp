@@ -442,27 +442,6 @@ int launch(dg_solver *h, const StageParams &p)
     return DG_OK;
 }
 
-int ensure_rk6(dg_solver *h)
-{
-    if (h->kx[0]) return DG_OK;
-    char *mem = nullptr;
-    if (!h->own_ws) {
-        if (h->ws_bytes < h->lay.rk6)
-            return fail(DG_ENOMEM, "workspace too small for RK6 (see dg_workspace_bytes)");
-        mem = h->ws + h->lay.base;
-    } else {
-        hipError_t e = hipMalloc((void **)&h->rk6_mem, 5 * h->lay.array);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            h->rk6_mem = nullptr;
-            return fail(DG_ENOMEM, "cannot allocate the RK6 stage store");
-        }
-        mem = h->rk6_mem;
-    }
-    for (int i = 0; i < 5; ++i) h->kx[i] = mem + i * h->lay.array;
-    return DG_OK;
-}
-
 int step_rk34(dg_solver *h, int rk, double dt)
 {
     for (int st = 0; st < stage_count(rk); ++st) {
@@ -537,50 +516,89 @@ const Rk6Tableau &rk6_tableau()
 // k_0..k_5 live in A, kx[0..4]; Y alternates between Ya and Yb.
 int step_rk6(dg_solver *h, double dt)
 {
-    const Rk6Tableau &t = rk6_tableau();
-    void *k[6] = {h->A, h->kx[0], h->kx[1], h->kx[2], h->kx[3], h->kx[4]};
-    void *Y[2] = {h->Ya, h->Yb};
     for (int s = 0; s < 7; ++s) {
-        StageParams p = base_params(h);
-        p.yin = s == 0 ? h->U : Y[(s - 1) % 2];
-        const double *num = s < 6 ? t.num[s + 1] : t.bnum;
-        const double den = s < 6 ? t.den[s + 1] : t.bden;
-        int o = 0;
-        if (s < 6) {                                   // k_s = dt R
-            set_out(p, 0, k[s], 0.0, 0.0, 0.0, dt);
-            o = 1;
-        }
-        // the combination: U first, then the stored k's with nonzero weights
-        std::vector<std::pair<const void *, double>> in;
-        in.push_back({h->U, 1.0});
-        for (int j = 0; j < s && j < 6; ++j)
-            if (num[j] != 0.0) in.push_back({k[j], num[j] / den});
-        if ((int)in.size() > 2 + kMaxExtraIn) return fail(DG_ENOTSUP, "too many RK6 stage inputs");
-        void *dst = s < 6 ? Y[s % 2] : h->U;
-        (o == 0 ? p.out0 : p.out1) = dst;
-        p.cy[o] = 0.0;
-        p.cr[o] = num[s] * dt / den;
-        p.nin = (int)std::min<size_t>(2, in.size());
-        p.in0 = in[0].first;
-        p.c0[o] = in[0].second;
-        if (in.size() > 1) {
-            p.in1 = in[1].first;
-            p.c1[o] = in[1].second;
-        }
+        StageParams p;
         ExtraIn x;
-        std::memset(&x, 0, sizeof(x));
-        for (size_t j = 2; j < in.size(); ++j) {
-            x.in[x.n] = in[j].first;
-            x.c[o][x.n] = in[j].second;
-            ++x.n;
-        }
-        p.nout = o + 1;
+        const int rc = rk6_stage(h, s, dt, p, x);
+        if (rc) return rc;
         DG_HIP(stage_x_fn(h->prec, h->eq, h->dim, h->N)(p, x, h->grid, h->stream), "RK6 stage kernel launch");
     }
     return DG_OK;
 }
 
 }  // namespace
+
+int ensure_rk6(dg_solver *h)
+{
+    if (h->kx[0]) return DG_OK;
+    char *mem = nullptr;
+    if (!h->own_ws) {
+        if (h->ws_bytes < h->lay.rk6)
+            return fail(DG_ENOMEM, "workspace too small for RK6 (see dg_workspace_bytes)");
+        mem = h->ws + h->lay.base;
+    } else {
+        hipError_t e = hipMalloc((void **)&h->rk6_mem, 5 * h->lay.array);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            h->rk6_mem = nullptr;
+            return fail(DG_ENOMEM, "cannot allocate the RK6 stage store");
+        }
+        mem = h->rk6_mem;
+    }
+    for (int i = 0; i < 5; ++i) h->kx[i] = mem + i * h->lay.array;
+    return DG_OK;
+}
+
+// Stage s of Luther's RK6 (eq. RK6) as one fused stage-kernel launch:
+// k_s = dt R(Y_s) (s < 6) and Y_{s+1} (or, at s = 6, the new U) =
+// U + (sum_j num_{s+1,j} k_j) / den_{s+1}, the k's with nonzero weights as
+// further inputs.
+int rk6_stage(const dg_solver *h, int s, double dt, StageParams &p, ExtraIn &x)
+{
+    const Rk6Tableau &t = rk6_tableau();
+    void *k[6] = {h->A, h->kx[0], h->kx[1], h->kx[2], h->kx[3], h->kx[4]};
+    void *Y[2] = {h->Ya, h->Yb};
+    p = base_params(h);
+    p.yin = s == 0 ? h->U : Y[(s - 1) % 2];
+    const double *num = s < 6 ? t.num[s + 1] : t.bnum;
+    const double den = s < 6 ? t.den[s + 1] : t.bden;
+    int o = 0;
+    if (s < 6) {                                   // k_s = dt R
+        set_out(p, 0, k[s], 0.0, 0.0, 0.0, dt);
+        o = 1;
+    }
+    // the combination: U first, then the stored k's with nonzero weights
+    const void *in_ptr[8];
+    double in_w[8];
+    int nin = 0;
+    in_ptr[nin] = h->U;
+    in_w[nin++] = 1.0;
+    for (int j = 0; j < s && j < 6; ++j)
+        if (num[j] != 0.0) {
+            in_ptr[nin] = k[j];
+            in_w[nin++] = num[j] / den;
+        }
+    if (nin > 2 + kMaxExtraIn) return fail(DG_ENOTSUP, "too many RK6 stage inputs");
+    void *dst = s < 6 ? Y[s % 2] : h->U;
+    (o == 0 ? p.out0 : p.out1) = dst;
+    p.cy[o] = 0.0;
+    p.cr[o] = num[s] * dt / den;
+    p.nin = std::min(2, nin);
+    p.in0 = in_ptr[0];
+    p.c0[o] = in_w[0];
+    if (nin > 1) {
+        p.in1 = in_ptr[1];
+        p.c1[o] = in_w[1];
+    }
+    std::memset(&x, 0, sizeof(x));
+    for (int j = 2; j < nin; ++j) {
+        x.in[x.n] = in_ptr[j];
+        x.c[o][x.n] = in_w[j];
+        ++x.n;
+    }
+    p.nout = o + 1;
+    return DG_OK;
+}
 
 int enqueue_steps(dg_solver *h, int rk, double dt, int64_t nsteps)
 {

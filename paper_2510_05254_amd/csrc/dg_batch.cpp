@@ -43,6 +43,7 @@ struct Member {
 struct Group {
     int prec = 0, eq = 0, dim = 0, N = 0, rk = 0, stages = 0;
     BatchFn fn = nullptr;
+    BatchXFn fnx = nullptr;        // RK6: fused stages with further inputs
     int nin[8] = {};               // RK inputs of each stage (same for every member)
     // 1-D classes step with the temporally blocked kernel: per member an
     // MsSolve (header, at off_params) and its workgroups; up to smax steps
@@ -55,7 +56,7 @@ struct Group {
     bool buf = true;
     std::vector<int> idx;          // member indices
     uint32_t ntiles = 0;
-    size_t off_params = 0, off_solve = 0, off_base = 0;
+    size_t off_params = 0, off_solve = 0, off_base = 0, off_extra = 0;
     const void *D = nullptr;
     const uint32_t *ftab = nullptr;
     int64_t grid = 0;
@@ -212,7 +213,21 @@ int rebuild(dg_batch *b)
             g.stages = stage_count(m.rk);
             g.fn = batch_fn(h->prec, h->eq, h->dim, h->N);
             if (!g.fn) return fail(DG_ENOTSUP, "no batched kernel for this class");
-            for (int s = 0; s < g.stages; ++s) g.nin[s] = stage_program(h, m.rk, s, m.dt).nin;
+            if (m.rk == DG_RK6) {
+                g.fnx = batch_x_fn(h->prec, h->eq, h->dim, h->N);
+                if (!g.fnx) return fail(DG_ENOTSUP, "no batched RK6 kernel for this class");
+            }
+            for (int s = 0; s < g.stages; ++s) {
+                if (m.rk != DG_RK6) {
+                    g.nin[s] = stage_program(h, m.rk, s, m.dt).nin;
+                    continue;
+                }
+                StageParams p;
+                ExtraIn x;
+                const int rc = rk6_stage(h, s, m.dt, p, x);
+                if (rc) return rc;
+                g.nin[s] = p.nin;
+            }
             if (ms_plan(h, m.rk).ok) {
                 g.ms = true;
                 g.msfn = ms_fn(h->prec, h->eq, h->N);
@@ -265,6 +280,8 @@ int rebuild(dg_batch *b)
         g.ntiles = (uint32_t)tiles;
         g.off_params = header;
         header = round_up(header + (g.ms ? sizeof(MsSolve) * n : sizeof(StageParams) * n * g.stages));
+        g.off_extra = header;
+        if (g.fnx) header = round_up(header + sizeof(ExtraIn) * n * g.stages);
         g.off_base = header;
         header = round_up(header + sizeof(uint32_t) * (n + 1));
         g.grid = std::min<int64_t>((int64_t)tiles, kMaxGrid);
@@ -308,7 +325,15 @@ int rebuild(dg_batch *b)
                 t0 += (uint32_t)pl.nwg;
                 continue;
             }
-            for (int s = 0; s < g.stages; ++s) par[s * n + j] = stage_program(m.h, m.rk, s, m.dt);
+            if (g.fnx) {
+                ExtraIn *ext = reinterpret_cast<ExtraIn *>(staging + g.off_extra);
+                for (int s = 0; s < g.stages; ++s) {
+                    const int rc = rk6_stage(m.h, s, m.dt, par[s * n + j], ext[s * n + j]);
+                    if (rc) return rc;
+                }
+            } else {
+                for (int s = 0; s < g.stages; ++s) par[s * n + j] = stage_program(m.h, m.rk, s, m.dt);
+            }
             t0 += (uint32_t)m.h->ntiles;
         }
         base[n] = t0;
@@ -361,7 +386,13 @@ int launch_tick(dg_batch *b, int k, hipStream_t st)
             L.xq = g.ntiles / kXcds;
             L.xr = g.ntiles % kXcds;
             L.nsolves = n;
-            DG_HIP(g.fn(L, g.buf, g.nin[s], g.grid, st), "batched stage kernel launch");
+            L.extra = nullptr;
+            if (g.fnx) {
+                L.extra = reinterpret_cast<const ExtraIn *>(b->dbuf + g.off_extra) + (size_t)s * n;
+                DG_HIP(g.fnx(L, g.buf, g.grid, st), "batched RK6 stage kernel launch");
+            } else {
+                DG_HIP(g.fn(L, g.buf, g.nin[s], g.grid, st), "batched stage kernel launch");
+            }
         }
     return DG_OK;
 }
@@ -438,8 +469,7 @@ int dg_batch_destroy(dg_batch *b)
 int dg_batch_add(dg_batch *b, dg_solver *h, int rk, double dt, int64_t nsteps)
 {
     if (!b || !h) return fail(DG_EINVAL, "NULL argument");
-    if (rk == DG_RK6) return fail(DG_ENOTSUP, "batched stepping supports DG_RK3 and DG_RK4");
-    if (rk != DG_RK3 && rk != DG_RK4) return fail(DG_EINVAL, "rk must be 3 or 4");
+    if (rk != DG_RK3 && rk != DG_RK4 && rk != DG_RK6) return fail(DG_EINVAL, "rk must be DG_RK3, DG_RK4 or DG_RK6");
     if (!std::isfinite(dt) || !(dt > 0.0)) return fail(DG_EINVAL, "dt must be finite and > 0");
     if (nsteps < 1) return fail(DG_EINVAL, "nsteps must be >= 1");
     if (!h->has_state) return fail(DG_ESTATE, "dg_set_state has not been called");
@@ -447,6 +477,7 @@ int dg_batch_add(dg_batch *b, dg_solver *h, int rk, double dt, int64_t nsteps)
     if (h->device != b->device) return fail(DG_EINVAL, "solver is on another device");
     int rc = select_device(h);
     if (rc) return rc;
+    if (rk == DG_RK6 && (rc = ensure_rk6(h))) return rc;
     // the batch's work on h follows everything already enqueued on h's stream
     if (h->stream != b->stream) {
         hipEvent_t ev;

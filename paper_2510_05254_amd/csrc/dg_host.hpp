@@ -137,6 +137,11 @@ struct MsPlan {
     int64_t T = 0;
     int64_t nwg = 0;
 };
+// The RK6 stage store (kx) of h: in h's workspace, or allocated by the library
+// for a library-owned workspace.
+int ensure_rk6(dg_solver *h);
+// Stage s (0..6) of the RK6 schedule as stage parameters and further inputs.
+int rk6_stage(const dg_solver *h, int s, double dt, StageParams &p, ExtraIn &x);
 MsPlan ms_plan(const dg_solver *h, int rk, int64_t tcap = 0);
 // compute units of a device (256 if the runtime does not say)
 int device_cus(int device);

@@ -6,6 +6,7 @@ namespace dg {
 StageFn stage_fn_f32_d1_adv(int N) { return pick_stage_n<float, 1, 0>(N); }
 StageXFn stage_x_fn_f32_d1_adv(int N) { return pick_stage_x_n<float, 1, 0>(N); }
 BatchFn batch_fn_f32_d1_adv(int N) { return pick_batch_n<float, 1, 0>(N); }
+BatchXFn batch_x_fn_f32_d1_adv(int N) { return pick_batch_x_n<float, 1, 0>(N); }
 MsFn ms_fn_f32_adv(int N) { return ms::pick_ms1<float, 0>(N); }
 int ms_cap_f32_adv(int N) { return ms::cap1<float, 0>(N); }
 }  // namespace dg

@@ -5,4 +5,5 @@ namespace dg {
 StageFn stage_fn_f64_d2_adv(int N) { return pick_stage_n<double, 2, 0>(N); }
 StageXFn stage_x_fn_f64_d2_adv(int N) { return pick_stage_x_n<double, 2, 0>(N); }
 BatchFn batch_fn_f64_d2_adv(int N) { return pick_batch_n<double, 2, 0>(N); }
+BatchXFn batch_x_fn_f64_d2_adv(int N) { return pick_batch_x_n<double, 2, 0>(N); }
 }  // namespace dg

@@ -5,4 +5,5 @@ namespace dg {
 StageFn stage_fn_f64_d3_euler(int N) { return pick_stage_n<double, 3, 1>(N); }
 StageXFn stage_x_fn_f64_d3_euler(int N) { return pick_stage_x_n<double, 3, 1>(N); }
 BatchFn batch_fn_f64_d3_euler(int N) { return pick_batch_n<double, 3, 1>(N); }
+BatchXFn batch_x_fn_f64_d3_euler(int N) { return pick_batch_x_n<double, 3, 1>(N); }
 }  // namespace dg

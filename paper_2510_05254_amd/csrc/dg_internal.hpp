@@ -82,6 +82,7 @@ struct BatchLaunch {
     const uint32_t *tile_base;   // first virtual tile of each solve (device)
     const void *D;               // differentiation matrix of the class (device)
     const uint32_t *ftab;        // face-point table of the class (device)
+    const struct ExtraIn *extra; // per solve, this stage's further inputs (RK6; device)
     uint32_t ntiles, xq, xr, nsolves;
 };
 
@@ -175,11 +176,14 @@ typedef hipError_t (*StageFn)(const StageParams &p, int64_t grid, hipStream_t s)
 typedef hipError_t (*StageXFn)(const StageParams &p, const ExtraIn &x, int64_t grid, hipStream_t s);
 // nin: the stage's number of RK inputs, the same for every solve of the launch
 typedef hipError_t (*BatchFn)(const BatchLaunch &b, bool buf, int nin, int64_t grid, hipStream_t s);
+// batched stage with further inputs (fused RK6 stages; b.extra set)
+typedef hipError_t (*BatchXFn)(const BatchLaunch &b, bool buf, int64_t grid, hipStream_t s);
 
 // Stage launcher for (precision, equation, dim, N); nullptr if not built.
 StageFn stage_fn(int precision, int equation, int dim, int N);
 StageXFn stage_x_fn(int precision, int equation, int dim, int N);
 BatchFn batch_fn(int precision, int equation, int dim, int N);
+BatchXFn batch_x_fn(int precision, int equation, int dim, int N);
 // Threads per block and elements per block of the stage kernel for (dim, N).
 int stage_threads(int dim, int N);
 int stage_epb(int dim, int N);

@@ -42,6 +42,18 @@ BatchFn batch_fn_f32_d2_adv(int N);
 BatchFn batch_fn_f32_d2_euler(int N);
 BatchFn batch_fn_f32_d3_adv(int N);
 BatchFn batch_fn_f32_d3_euler(int N);
+BatchXFn batch_x_fn_f64_d1_adv(int N);
+BatchXFn batch_x_fn_f64_d1_euler(int N);
+BatchXFn batch_x_fn_f64_d2_adv(int N);
+BatchXFn batch_x_fn_f64_d2_euler(int N);
+BatchXFn batch_x_fn_f64_d3_adv(int N);
+BatchXFn batch_x_fn_f64_d3_euler(int N);
+BatchXFn batch_x_fn_f32_d1_adv(int N);
+BatchXFn batch_x_fn_f32_d1_euler(int N);
+BatchXFn batch_x_fn_f32_d2_adv(int N);
+BatchXFn batch_x_fn_f32_d2_euler(int N);
+BatchXFn batch_x_fn_f32_d3_adv(int N);
+BatchXFn batch_x_fn_f32_d3_euler(int N);
 
 MsFn ms_fn_f64_adv(int N);
 MsFn ms_fn_f64_euler(int N);
@@ -76,6 +88,21 @@ BatchFn batch_fn(int precision, int equation, int dim, int N)
         {{batch_fn_f32_d1_adv, batch_fn_f32_d1_euler},
          {batch_fn_f32_d2_adv, batch_fn_f32_d2_euler},
          {batch_fn_f32_d3_adv, batch_fn_f32_d3_euler}}};
+    if (precision < 0 || precision > 1 || equation < 0 || equation > 1 || dim < 1 || dim > 3)
+        return nullptr;
+    return table[precision][dim - 1][equation](N);
+}
+
+BatchXFn batch_x_fn(int precision, int equation, int dim, int N)
+{
+    typedef BatchXFn (*Pick)(int);
+    static const Pick table[2][3][2] = {
+        {{batch_x_fn_f64_d1_adv, batch_x_fn_f64_d1_euler},
+         {batch_x_fn_f64_d2_adv, batch_x_fn_f64_d2_euler},
+         {batch_x_fn_f64_d3_adv, batch_x_fn_f64_d3_euler}},
+        {{batch_x_fn_f32_d1_adv, batch_x_fn_f32_d1_euler},
+         {batch_x_fn_f32_d2_adv, batch_x_fn_f32_d2_euler},
+         {batch_x_fn_f32_d3_adv, batch_x_fn_f32_d3_euler}}};
     if (precision < 0 || precision > 1 || equation < 0 || equation > 1 || dim < 1 || dim > 3)
         return nullptr;
     return table[precision][dim - 1][equation](N);

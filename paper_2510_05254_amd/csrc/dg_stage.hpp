@@ -784,19 +784,24 @@ stage_kernel_x(const StageParams p, const ExtraIn x)
 // precision, equation, dimension, degree; meshes, arrays and time steps
 // differ). Virtual tile T (XCD-contiguous numbering over all solves) belongs
 // to solve tile_solve[T] and is that solve's tile T - tile_base[solve].
+// The LDS layout and register target are the single-solve kernel's for the
+// class (stage_vel, stage_waves).
 template <typename real, int DIM, int N, int EQ, bool BUF, int NIN>
-__global__ void __launch_bounds__((Geo<DIM, N>::THREADS)) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__((Geo<DIM, N>::THREADS))
+__attribute__((amdgpu_waves_per_eu(stage_waves(DIM, N, EQ, (int)sizeof(real), BUF))))
 stage_kernel_batch(const BatchLaunch b)
 {
     using G = Geo<DIM, N>;
-    __shared__ StageLds<real, DIM, N, EQ, 1, false> lds;
+    constexpr int W = stage_waves(DIM, N, EQ, (int)sizeof(real), BUF);
+    constexpr bool VEL = stage_vel(DIM, N, EQ, (int)sizeof(real), BUF);
+    __shared__ StageLds<real, DIM, N, EQ, 1, VEL> lds;
     const ThreadSetup<DIM, N, 1> ts;
     const real dval = ts.tid < G::N1 * G::N1 ? static_cast<const real *>(b.D)[ts.tid] : real(0);
     for (uint32_t vb = blockIdx.x; vb < b.ntiles; vb += gridDim.x) {
         const uint32_t xb = vb & (kXcds - 1), jb = vb / kXcds;
         const uint32_t T = xb * b.xq + (xb < b.xr ? xb : b.xr) + jb;
         const uint32_t s = b.tile_solve[T];
-        stage_tile<real, DIM, N, EQ, BUF, 1, false, NIN>(b.params[s], T - b.tile_base[s], lds, ts, dval);
+        stage_tile<real, DIM, N, EQ, BUF, 1, false, NIN, W, VEL>(b.params[s], T - b.tile_base[s], lds, ts, dval);
         __syncthreads();
     }
 }
@@ -821,6 +826,36 @@ hipError_t launch_stage(const StageParams &p, int64_t grid, hipStream_t s)
         launch_stage_nin<real, DIM, N, EQ, true>(p, grid, s);
     else
         launch_stage_nin<real, DIM, N, EQ, false>(p, grid, s);
+    return hipGetLastError();
+}
+
+// Batched fused RK6 stage: stage_kernel_x's body per member, the member's
+// further inputs from b.extra.
+template <typename real, int DIM, int N, int EQ, bool BUF>
+__global__ void __launch_bounds__((Geo<DIM, N>::THREADS)) __attribute__((amdgpu_waves_per_eu(4)))
+stage_kernel_batch_x(const BatchLaunch b)
+{
+    using G = Geo<DIM, N>;
+    __shared__ StageLds<real, DIM, N, EQ, 1, false> lds;
+    const ThreadSetup<DIM, N, 1> ts;
+    const real dval = ts.tid < G::N1 * G::N1 ? static_cast<const real *>(b.D)[ts.tid] : real(0);
+    for (uint32_t vb = blockIdx.x; vb < b.ntiles; vb += gridDim.x) {
+        const uint32_t xb = vb & (kXcds - 1), jb = vb / kXcds;
+        const uint32_t T = xb * b.xq + (xb < b.xr ? xb : b.xr) + jb;
+        const uint32_t s = b.tile_solve[T];
+        stage_tile<real, DIM, N, EQ, BUF, 1, true>(b.params[s], T - b.tile_base[s], lds, ts, dval, b.extra + s);
+        __syncthreads();
+    }
+}
+
+template <typename real, int DIM, int N, int EQ>
+hipError_t launch_stage_batch_x(const BatchLaunch &b, bool buf, int64_t grid, hipStream_t s)
+{
+    const dim3 g((unsigned)grid), t(Geo<DIM, N>::THREADS);
+    if (buf)
+        hipLaunchKernelGGL((stage_kernel_batch_x<real, DIM, N, EQ, true>), g, t, 0, s, b);
+    else
+        hipLaunchKernelGGL((stage_kernel_batch_x<real, DIM, N, EQ, false>), g, t, 0, s, b);
     return hipGetLastError();
 }
 
@@ -887,6 +922,22 @@ BatchFn pick_batch_n(int N)
     case 6: return &launch_stage_batch<real, DIM, 6, EQ>;
     case 7: return &launch_stage_batch<real, DIM, 7, EQ>;
     case 8: return &launch_stage_batch<real, DIM, 8, EQ>;
+    default: return nullptr;
+    }
+}
+
+template <typename real, int DIM, int EQ>
+BatchXFn pick_batch_x_n(int N)
+{
+    switch (N) {
+    case 1: return &launch_stage_batch_x<real, DIM, 1, EQ>;
+    case 2: return &launch_stage_batch_x<real, DIM, 2, EQ>;
+    case 3: return &launch_stage_batch_x<real, DIM, 3, EQ>;
+    case 4: return &launch_stage_batch_x<real, DIM, 4, EQ>;
+    case 5: return &launch_stage_batch_x<real, DIM, 5, EQ>;
+    case 6: return &launch_stage_batch_x<real, DIM, 6, EQ>;
+    case 7: return &launch_stage_batch_x<real, DIM, 7, EQ>;
+    case 8: return &launch_stage_batch_x<real, DIM, 8, EQ>;
     default: return nullptr;
     }
 }

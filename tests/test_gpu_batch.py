@@ -26,8 +26,7 @@ MIX = [  # (dim, N, K, eq, rk, nsteps)
     (3, 2, (4, 3, 5), EUL, 4, 3),
     (3, 4, (3, 2, 2), EUL, 4, 18),
     (3, 4, (2, 3, 1), EUL, 4, 7),  # same class: 2 x 2 tiles, ragged last row
-    # single solves of these classes use the velocity LDS layout and/or the
-    # six-wave register target, the batch kernel the tensor layout: bitwise
+    # classes with the velocity LDS layout and/or the six-wave register target
     (3, 1, (40, 3, 2), EUL, 4, 3),
     (3, 6, (2, 2, 1), EUL, 3, 2),
     (3, 7, (2, 1, 2), EUL, 4, 2),
@@ -35,6 +34,11 @@ MIX = [  # (dim, N, K, eq, rk, nsteps)
     (1, 5, (10,), EUL, 3, 5),
     (1, 7, (1500,), ADV, 4, 27),   # 1-D, chunked: several multi-step launches
     (1, 7, (90,), ADV, 4, 9),      # same class, held whole by one workgroup
+    # RK6 members: fused stages with further inputs, one launch per stage
+    (1, 4, (50,), ADV, 6, 3),
+    (2, 3, (6, 5), EUL, 6, 2),
+    (2, 3, (4, 7), EUL, 6, 5),     # same class, other mesh, dt and step count
+    (3, 2, (3, 2, 2), EUL, 6, 2),
 ]
 
 
@@ -140,10 +144,17 @@ def test_continuous_admission_and_graph_replays():
 def test_batch_error_paths():
     s, U0, dt = _solver_with_state(2, 2, (3, 3), ADV, 3)
     fresh = dg.Solver(2, 2, (3, 3), ADV, params(2, ADV))
+    # an RK6 member needs the RK6 stage store: an external workspace sized
+    # for RK4 cannot hold it
+    import torch
+    ws4 = dg.dg_workspace_bytes(2, 2, (3, 3), ADV, dg.DG_FP64, 4)
+    buf = torch.empty(ws4, dtype=torch.uint8, device="cuda")
+    small = dg.Solver(2, 2, (3, 3), ADV, params(2, ADV), device_workspace=buf.data_ptr(), workspace_bytes=ws4)
+    small.set_state(U0)
     with dg.Batch() as b:
         with pytest.raises(dg.DgError) as e:
-            b.add(s, 6, dt, 2)
-        assert e.value.status == dg.DG_ENOTSUP
+            b.add(small, 6, dt, 2)
+        assert e.value.status == dg.DG_ENOMEM
         with pytest.raises(dg.DgError) as e:
             b.add(fresh, 4, dt, 2)
         assert e.value.status == dg.DG_ESTATE
@@ -169,3 +180,4 @@ def test_batch_error_paths():
         assert b.size() == (0, 0)
         assert b.run(10) == 0
     fresh.close()
+    small.close()
