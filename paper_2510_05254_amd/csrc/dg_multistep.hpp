@@ -151,6 +151,10 @@ ms1_kernel(const MsLaunch l)
     const int64_t gfirst = own0 - H;                        // global element of local 0
     const real par = uni(real(P->par)), rdx2 = uni(real(P->rdx2));
     const real sl = rdx2 * INVW0;
+    // lift weight and face of this thread's node: node 0 lifts +sl from face
+    // le, node N -sl from face le + 1, interior nodes nothing
+    const real lw = i == 0 ? sl : (i == N ? -sl : real(0));
+    const int fo = i == N ? 1 : 0;
 
     // the stage coefficients, read once
     if (tid < 32) sC[tid >> 3][(tid >> 2) & 1][tid & 3] = real(P->coef[tid >> 3][(tid >> 2) & 1][tid & 3]);
@@ -238,8 +242,9 @@ ms1_kernel(const MsLaunch l)
 #pragma unroll
                     for (int v = 0; v < NV; ++v) R[v] -= rdx2 * acc[v];
                 }
-                // lifts at the end nodes: +-(2/dx)(1/w_0)(Fhat - F)
-                if (i == 0 || i == N) {
+                // lifts at the end nodes: +-(2/dx)(1/w_0)(Fhat - F), taken by
+                // every lane without a branch (lw = 0 off the end nodes)
+                {
                     real F[NV];
                     if constexpr (EQ == 0) {
                         real lam;
@@ -248,14 +253,10 @@ ms1_kernel(const MsLaunch l)
 #pragma unroll
                         for (int v = 0; v < NV; ++v) F[v] = sF[v][base + i];
                     }
-                    if (i == 0) {
+                    int fi = le + fo;
+                    fi = whole && fi == L ? 0 : fi;
 #pragma unroll
-                        for (int v = 0; v < NV; ++v) R[v] += sl * (sH[v][le] - F[v]);
-                    } else {
-                        const int fu = whole && le == L - 1 ? 0 : le + 1;
-#pragma unroll
-                        for (int v = 0; v < NV; ++v) R[v] += -sl * (sH[v][fu] - F[v]);
-                    }
+                    for (int v = 0; v < NV; ++v) R[v] += lw * (sH[v][fi] - F[v]);
                 }
                 // RK stage combination at node i (the outputs never alias the
                 // stage input; an output that is also an input is this node's)

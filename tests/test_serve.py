@@ -114,3 +114,13 @@ def test_first_fit_random_no_overlap():
     for blk in live:
         a.release(*blk)
     assert a.free == [(0, a.nbytes)]
+
+
+def test_fifo_rebuild_of_one_at_a_time_server():
+    """The one-at-a-time timeline rebuilt from service times: a request starts
+    when it has arrived and the previous one has finished."""
+    from paper_2510_05254_amd.serve_runs import fifo
+    lat, end = fifo([1.0, 2.0, 3.0], [0.0, 0.0, 0.0])
+    assert lat == [1.0, 3.0, 6.0] and end == 6.0
+    lat, end = fifo([1.0, 1.0, 1.0], [0.0, 5.0, 5.5])     # idle gap, then a queue
+    assert lat == [1.0, 1.0, 1.5] and end == 7.0
