@@ -198,11 +198,14 @@ int dg_l2_error_vars(dg_solver *h, const double *u_ref, int64_t count, double *s
  * of the conservation law of Sec. 2.1, eq. scalar_cons), FP64; waits. */
 int dg_mass(dg_solver *h, double *mass);
 
-/* Wait for all work enqueued on the solver's stream (no computation). */
+/* Wait for all work enqueued on the solver's stream (no computation); for a
+ * batch member also for the batch work enqueued so far. */
 int dg_synchronize(dg_solver *h);
 
 /* The solver's hipStream_t (as void*), for stream-ordered interop; NULL for
- * a NULL handle. */
+ * a NULL handle. For a batch member the stream is first made to wait for the
+ * batch work enqueued so far (work the batch enqueues later is not ordered
+ * before what the caller then puts on the stream: call dg_stream again). */
 void *dg_stream(const dg_solver *h);
 
 /* Autotune the launch configuration (no change to the method: every
@@ -280,8 +283,11 @@ int dg_batch_destroy(dg_batch *b);
  * step dt > 0. RK6 members need the RK6 stage store as dg_step does (an
  * external workspace of dg_workspace_bytes(..., DG_RK6), else DG_ENOMEM; a
  * library-owned one allocates it here). While a member, h must not be stepped
- * or have its state set directly (DG_ESTATE); dg_get_state / dg_l2_error /
- * dg_mass on it are stream-ordered after the batch work enqueued so far. */
+ * or have its state set directly (DG_ESTATE); dg_get_state,
+ * dg_get_state_device, dg_l2_error, dg_mass, dg_synchronize and dg_stream on
+ * it are stream-ordered after the batch work enqueued so far (h's stream
+ * waits for the batch when h is read, not after every dg_batch_run), and
+ * dg_get_state_device's copy is ordered before later batch work. */
 int dg_batch_add(dg_batch *b, dg_solver *h, int rk, double dt, int64_t nsteps);
 
 /* Remove member h (finished or not); its remaining steps are dropped. */

@@ -885,6 +885,7 @@ int dg_get_state(dg_solver *h, double *u, int64_t count)
     int rc = check_count(h, count);
     if (rc || (rc = select_device(h))) return rc;
     if (!h->has_state) return fail(DG_ESTATE, "dg_set_state has not been called");
+    if ((rc = batch_order_member(h))) return rc;
     const void *src = h->U;
     if (!(h->prec == DG_FP64 && h->nvar == 1)) {
         // converted to variable-major FP64 in the free RK arrays first
@@ -903,13 +904,15 @@ int dg_get_state_device(dg_solver *h, void *u_dev, int64_t count)
     int rc = check_count(h, count);
     if (rc || (rc = select_device(h))) return rc;
     if (!h->has_state) return fail(DG_ESTATE, "dg_set_state has not been called");
+    if ((rc = batch_order_member(h))) return rc;
     if (h->prec == DG_FP64 && h->nvar == 1) {
         DG_HIP(hipMemcpyAsync(u_dev, h->U, sizeof(double) * count, hipMemcpyDeviceToDevice, h->stream),
                "hipMemcpyAsync");
     } else if ((rc = convert(h, h->U, h->prec, u_dev, DG_FP64, false))) {
         return rc;
     }
-    return DG_OK;
+    // later batch work (which rewrites U and the conversion's staging) waits
+    return batch_after_member(h);
 }
 
 int dg_l2_error_vars(dg_solver *h, const double *u_ref, int64_t count, double *sq_err, double *sq_ref)
@@ -918,6 +921,7 @@ int dg_l2_error_vars(dg_solver *h, const double *u_ref, int64_t count, double *s
     int rc = check_count(h, count);
     if (rc || (rc = select_device(h))) return rc;
     if (!h->has_state) return fail(DG_ESTATE, "dg_set_state has not been called");
+    if ((rc = batch_order_member(h))) return rc;
     double *dref = nullptr;
     if ((rc = stage_reference(h, u_ref, &dref))) return rc;
     return reduce(h, 1, dref, sq_err, sq_ref);
@@ -945,6 +949,7 @@ int dg_mass(dg_solver *h, double *mass)
     int rc = select_device(h);
     if (rc) return rc;
     if (!h->has_state) return fail(DG_ESTATE, "dg_set_state has not been called");
+    if ((rc = batch_order_member(h))) return rc;
     return reduce(h, 0, nullptr, mass, nullptr);
 }
 
@@ -952,7 +957,7 @@ int dg_synchronize(dg_solver *h)
 {
     if (!h) return fail(DG_EINVAL, "solver is NULL");
     int rc = select_device(h);
-    if (rc) return rc;
+    if (rc || (rc = batch_order_member(h))) return rc;
     DG_HIP(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
     return DG_OK;
 }
@@ -1120,6 +1125,13 @@ int dg_set_launch_config(dg_solver *h, const int64_t *cfg, int n)
     return DG_OK;
 }
 
-void *dg_stream(const dg_solver *h) { return h ? static_cast<void *>(h->stream) : nullptr; }
+void *dg_stream(const dg_solver *h)
+{
+    if (!h) return nullptr;
+    // a member's stream is handed out ordered after the batch work so far
+    if (h->batch && (select_device(h) != DG_OK || batch_order_member(const_cast<dg_solver *>(h)) != DG_OK))
+        return nullptr;
+    return static_cast<void *>(h->stream);
+}
 
 }  // extern "C"

@@ -398,15 +398,40 @@ int launch_tick(dg_batch *b, int k, hipStream_t st)
 }
 
 // Member streams wait for the batch work enqueued so far.
+// The batch work enqueued so far ends at `done`; a member's stream waits for it
+// when the member is read (batch_order_member), not after every run, so a run
+// costs O(1) stream operations however many members the batch has.
 int publish(dg_batch *b)
 {
     DG_HIP(hipEventRecord(b->done, b->stream), "hipEventRecord");
-    for (const Member &m : b->members)
-        if (m.h->stream != b->stream) DG_HIP(hipStreamWaitEvent(m.h->stream, b->done, 0), "hipStreamWaitEvent");
     return DG_OK;
 }
 
 }  // namespace
+
+namespace dg {
+
+int batch_order_member(dg_solver *h)
+{
+    dg_batch *b = h->batch;
+    if (b && h->stream != b->stream) DG_HIP(hipStreamWaitEvent(h->stream, b->done, 0), "hipStreamWaitEvent");
+    return DG_OK;
+}
+
+int batch_after_member(dg_solver *h)
+{
+    dg_batch *b = h->batch;
+    if (!b || h->stream == b->stream) return DG_OK;
+    hipEvent_t ev;
+    DG_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "hipEventCreate");
+    hipError_t e = hipEventRecord(ev, h->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, ev, 0);
+    (void)hipEventDestroy(ev);
+    if (e != hipSuccess) return hip_fail(e, "stream ordering");
+    return DG_OK;
+}
+
+}  // namespace dg
 
 extern "C" {
 
@@ -499,7 +524,7 @@ int dg_batch_remove(dg_batch *b, dg_solver *h)
     const int i = member_index(b, h);
     if (i < 0) return fail(DG_EINVAL, "solver is not a member of this batch");
     int rc = publish(b);
-    if (rc) return rc;
+    if (rc || (rc = batch_order_member(h))) return rc;
     const bool active = b->members[i].remaining > 0;
     b->members.erase(b->members.begin() + i);
     h->batch = nullptr;

@@ -137,6 +137,11 @@ struct MsPlan {
     int64_t T = 0;
     int64_t nwg = 0;
 };
+// Batch members: before h's state is read on h's stream, that stream waits
+// for the batch work enqueued so far; after an asynchronous read, the batch
+// stream waits for the read (no-ops for a solver outside a batch).
+int batch_order_member(dg_solver *h);
+int batch_after_member(dg_solver *h);
 // The RK6 stage store (kx) of h: in h's workspace, or allocated by the library
 // for a library-owned workspace.
 int ensure_rk6(dg_solver *h);

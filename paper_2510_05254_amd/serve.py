@@ -207,13 +207,16 @@ class Server:
         blk = self.arena.alloc(ws)
         if blk is None:
             return False
-        # each admitted solver gets a stream of its own (hip_stream=None):
-        # creating it and setting its state wait for that fresh stream only,
-        # not for the ticks in flight on the batch stream, which dg_batch_add
-        # orders after the member's stream (a stream shared by all members
-        # would wait for every run, since each run makes member streams
-        # wait for the batch)
-        s = dg.Solver(r.dim, r.N, r.K, r.eq, r.params, precision=dg.DG_FP64, hip_stream=None,
+        # admitted solvers run their setup on streams of torch's stream pool,
+        # not on the batch stream: creating a solver and setting its state
+        # then wait for earlier admissions only, not for the ticks in flight
+        # (dg_batch_add orders the batch stream after the member's stream; a
+        # member's stream waits for the batch only when the member is read)
+        import torch
+        st = torch.cuda.Stream()
+        if st.cuda_stream == self.stream.cuda_stream:     # the pool hands out streams in turn
+            st = torch.cuda.Stream()
+        s = dg.Solver(r.dim, r.N, r.K, r.eq, r.params, precision=dg.DG_FP64, hip_stream=st.cuda_stream,
                       device_workspace=self.arena.base + blk[0], workspace_bytes=blk[1])
         s._ws = self.arena.buf                  # the arena outlives the solver
         s.set_state(U0)
