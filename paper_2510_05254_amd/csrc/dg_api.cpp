@@ -212,32 +212,10 @@ int device_cus(int device)
 
 MsPlan ms_plan(const dg_solver *h, int rk, int64_t tcap)
 {
-    MsPlan pl;
     if (h->dim != 1 || (rk != DG_RK3 && rk != DG_RK4) || !ms_fn(h->prec, h->eq, h->N) ||
         !ms_program_matches(ms_program(h, rk), rk))
-        return pl;
-    const int64_t cap = ms_capacity(h->prec, h->eq, h->N);
-    const int64_t K = h->K[0];
-    const int64_t stages = stage_count(rk);
-    if (K <= cap && K * h->n1 <= kMsWholeNodes) {
-        pl.whole = 1;
-        pl.smax = kMsWholeSteps;
-        pl.T = K;
-        pl.nwg = 1;
-    } else {
-        pl.smax = (int)std::max<int64_t>(1, cap / (int64_t(h->ms_div) * stages));
-        if (tcap > 0 && tcap + 2 * stages <= cap) {
-            // T = tcap; as many steps per launch as the bound and the halos allow
-            pl.T = tcap;
-            pl.smax = (int)std::max<int64_t>(1, std::min<int64_t>(pl.smax, (cap - tcap) / (2 * stages)));
-        } else {
-            pl.T = cap - 2 * stages * pl.smax;
-        }
-        pl.nwg = (K + pl.T - 1) / pl.T;
-        if (pl.T < 1 || pl.nwg > (int64_t(1) << 31)) return MsPlan();
-    }
-    pl.ok = true;
-    return pl;
+        return MsPlan();
+    return ms_plan_for(h->K[0], h->n1, ms_capacity(h->prec, h->eq, h->N), stage_count(rk), h->ms_div, tcap);
 }
 
 MsProgram ms_program(const dg_solver *h, int rk)
@@ -276,21 +254,6 @@ bool ms_program_matches(const MsProgram &g, int rk)
             if (g.out[st][o] != t.out[st][o]) return false;
     }
     return true;
-}
-
-MsSchedule ms_schedule(int64_t nsteps, int smax, bool even)
-{
-    MsSchedule s;
-    s.count = (nsteps + smax - 1) / smax;
-    if (even && (s.count & 1)) {
-        if (nsteps > s.count)
-            ++s.count;
-        else
-            s.copy = true;
-    }
-    s.base = s.count ? nsteps / s.count : 0;
-    s.extra = s.count ? nsteps % s.count : 0;
-    return s;
 }
 
 MsSolve ms_solve(const dg_solver *h, int rk, double dt, const MsPlan &pl, bool pingpong)

@@ -8,6 +8,7 @@
 
 #include "../../include/dg.h"
 #include "dg_internal.hpp"
+#include "dg_msplan.hpp"
 
 namespace dg {
 
@@ -120,23 +121,6 @@ int stage_count(int rk);
 // Parameters of fused stage s of the RK3/RK4 schedule with step dt.
 StageParams stage_program(const dg_solver *h, int rk, int s, double dt, bool zmarch = false);
 
-// 1-D multi-step plan: whole mode (one workgroup holds the periodic mesh,
-// up to kMsWholeSteps steps per launch) when the mesh fits in one
-// workgroup's LDS with at most kMsWholeNodes nodes; otherwise chunked, with T
-// owned elements per workgroup and at most smax steps per launch (the halo is
-// stages * smax elements per side, at most capacity / ms_div).
-// tcap > 0 asks for T = tcap (one round of workgroups over the GPU's CUs:
-// a chunk per CU), with smax lowered as far as the halos then need to fit;
-// a tcap that cannot fit is ignored.
-constexpr int kMsWholeSteps = 4096;
-constexpr int64_t kMsWholeNodes = 512;
-struct MsPlan {
-    bool ok = false;
-    int whole = 0;
-    int smax = 0;
-    int64_t T = 0;
-    int64_t nwg = 0;
-};
 // Batch members: before h's state is read on h's stream, that stream waits
 // for the batch work enqueued so far; after an asynchronous read, the batch
 // stream waits for the read (no-ops for a solver outside a batch).
@@ -147,11 +131,11 @@ int batch_after_member(dg_solver *h);
 int ensure_rk6(dg_solver *h);
 // Stage s (0..6) of the RK6 schedule as stage parameters and further inputs.
 int rk6_stage(const dg_solver *h, int s, double dt, StageParams &p, ExtraIn &x);
+// 1-D multi-step plan of h for scheme rk (ms_plan_for, after checking that
+// the kernel exists and its stage program is the host's); tcap as there.
 MsPlan ms_plan(const dg_solver *h, int rk, int64_t tcap = 0);
 // compute units of a device (256 if the runtime does not say)
 int device_cus(int device);
-// the owned elements per workgroup that spread `elements` over `cus` CUs
-inline int64_t ms_spread(int64_t elements, int cus) { return (elements + cus - 1) / cus; }
 // Stage program of scheme rk as array indices (0 U, 1 A, 2 Ya, 3 Yb).
 MsProgram ms_program(const dg_solver *h, int rk);
 // whether a stage program is the multi-step kernel's kMsProgRk3/kMsProgRk4
@@ -160,17 +144,6 @@ bool ms_program_matches(const MsProgram &g, int rk);
 // pingpong: the solve's launches alternate between U and Ya (V = Ya), else
 // update U in place (V = U; only for a mesh held by one workgroup)
 MsSolve ms_solve(const dg_solver *h, int rk, double dt, const MsPlan &pl, bool pingpong);
-// Launches for nsteps steps at most smax per launch. With ping-pong arrays
-// (even) the count is made even so that the state ends in U: the steps are
-// spread evenly over one more launch, or, when every launch already runs a
-// single step, a final copy launch (0 steps) is added.
-struct MsSchedule {
-    int64_t count = 0;               // launches that step
-    int64_t base = 0, extra = 0;     // launch i runs base + (i < extra) steps
-    bool copy = false;               // a trailing 0-step launch
-    int64_t launches() const { return count + (copy ? 1 : 0); }
-    int steps(int64_t i) const { return i < count ? int(base + (i < extra ? 1 : 0)) : 0; }
-};
-MsSchedule ms_schedule(int64_t nsteps, int smax, bool even);
+
 
 }  // namespace dg
