@@ -58,6 +58,9 @@ struct Geo1 {
     static constexpr int WAVES = BIG ? 8 : 4;
     static constexpr int THREADS = N1 * ((BIG ? 1024 : 512) / N1);
     static constexpr int EPP = THREADS / N1;                           // elements per pass
+    // advection meshes held whole take a one-barrier stage (where the extra
+    // code path fits the register budget without spilling)
+    static constexpr bool WHOLE1 = EQ == 0 && (sizeof(real) == 4 || N <= 4);
 };
 
 __device__ __forceinline__ double rcp_nr(double x)
@@ -187,6 +190,47 @@ ms1_kernel(const MsLaunch l)
                 c0[o] = uni(sC[st][o][1]);
                 c1[o] = uni(sC[st][o][2]);
                 cr[o] = uni(sC[st][o][3]);
+            }
+            if constexpr (G::WHOLE1) {
+                if (whole) {
+                    // a whole advection mesh: each end node evaluates its face
+                    // itself from the face's (lower, upper) pair (the bits of
+                    // the face phase), so the stage needs one barrier
+                    for (int le = e0; le < L; le += EPP) {
+                        const int base = le * S;
+                        real acc = real(0);
+#pragma unroll
+                        for (int m = 0; m < N1; ++m) acc += d[m] * sA[yi][0][base + m];
+                        real u[1] = {sA[yi][0][base + i]}, R = real(0), F[1], lam;
+                        R -= rdx2 * (par * acc);
+                        flux1<real, EQ>(u, par, F, lam);
+                        real Fh[1] = {F[0]};
+                        if (i == 0 || i == N) {
+                            const int el = i == 0 ? (le == 0 ? L - 1 : le - 1) : le;
+                            const int eu = i == 0 ? le : (le == L - 1 ? 0 : le + 1);
+                            real UL[1] = {sA[yi][0][el * S + N]}, UR[1] = {sA[yi][0][eu * S]};
+                            real FL[1], FR[1], lamL, lamR;
+                            flux1<real, EQ>(UL, par, FL, lamL);
+                            flux1<real, EQ>(UR, par, FR, lamR);
+                            lf_flux<real, 1>(UL, FL, lamL, UR, FR, lamR, Fh);
+                        }
+                        R += lw * (Fh[0] - F[0]);
+                        const real a0 = nin > 0 ? sA[i0][0][base + i] : real(0);
+                        const real a1 = nin > 1 ? sA[i1][0][base + i] : real(0);
+#pragma unroll
+                        for (int o = 0; o < 2; ++o) {
+                            if (o < nout) {
+                                real val = cy[o] * u[0];
+                                if (nin > 0) val += c0[o] * a0;
+                                if (nin > 1) val += c1[o] * a1;
+                                val += cr[o] * R;
+                                sA[PG.out[st][o]][0][base + i] = val;
+                            }
+                        }
+                    }
+                    __syncthreads();
+                    continue;
+                }
             }
             // ---- phase 1: eq. LF on every face the stage needs, once per face
             // from its (lower, upper) pair (face f joins elements f-1 and f;
