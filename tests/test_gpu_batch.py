@@ -181,3 +181,30 @@ def test_batch_error_paths():
         assert b.run(10) == 0
     fresh.close()
     small.close()
+
+
+def test_reading_an_active_member_mid_run():
+    """A member read on the device while the batch still has steps for it sees
+    the state after the steps enqueued so far, and the batch's later steps
+    (which rewrite its arrays, including the staging the read converts
+    through) wait for that read."""
+    import torch
+    specs = [(2, 3, (6, 5), EUL, 11), (1, 6, (900,), ADV, 11), (3, 2, (3, 2, 2), EUL, 11)]
+    made = [_solver_with_state(*sp[:4], 300 + i) for i, sp in enumerate(specs)]
+    with dg.Batch() as b:
+        for (s, U0, dt), sp in zip(made, specs):
+            b.add(s, 4, dt, sp[4])
+        assert b.run(4) == 4
+        mids = []
+        for s, U0, dt in made:
+            out = torch.empty(U0.size, dtype=torch.float64, device="cuda")
+            s.get_state_device(out)                 # asynchronous, on the member's stream
+            mids.append(out)
+        b.run(1 << 40)                              # the remaining 7 steps, enqueued after the reads
+        b.synchronize()
+        for (s, U0, dt), sp, out in zip(made, specs, mids):
+            s.synchronize()
+            np.testing.assert_array_equal(out.cpu().numpy().reshape(U0.shape), _alone(*sp[:4], U0, 4, dt, 4))
+            np.testing.assert_array_equal(s.get_state(), _alone(*sp[:4], U0, 4, dt, sp[4]))
+    for s, _, _ in made:
+        s.close()
