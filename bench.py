@@ -339,7 +339,7 @@ def main():
         "timing": head["timing"],
         "launch_config": {"tile_order": "plain" if lc[0] else "xcd_contiguous",
                           "z_slab": lc[1], "halo_divisor_1d": lc[2],
-                          "x_block": lc[4], "z_march": lc[5], "autotuned": bool(lc[3])},
+                          "x_block": lc[4], "z_march": lc[5], "chunk_1d": lc[6], "autotuned": bool(lc[3])},
         "nodes_per_s": head["nodes_per_s"],
         "copy_gbps": copy_gbs,
         "mass_drift": head["mass_drift"],

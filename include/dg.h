@@ -215,8 +215,9 @@ void *dg_stream(const dg_solver *h);
  * arrays, restarting from a saved copy of the state, restores the state and
  * keeps the fastest candidate for later dg_step calls. Candidates: 3-D, the
  * tile order (XCD-contiguous or plain) x the z-slab size x the x-block
- * width; 2-D, the tile order; 1-D RK3/RK4 meshes split into chunks, the
- * steps per launch (via the halo bound). Every candidate computes the same
+ * width, then the z-march length; 2-D, the tile order; 1-D RK3/RK4 meshes
+ * split into chunks, the elements per workgroup (cfg[6]) x the steps per
+ * launch (via the halo bound). Every candidate computes the same
  * results bit for bit; only speed differs. Synchronous. The tuner keeps
  * one copy of the state: a library-owned workspace allocates it; an external
  * workspace must hold it after the scheme's arrays, i.e. be at least
@@ -234,15 +235,19 @@ int dg_autotune(dg_solver *h, int rk, double dt, int trial_steps);
  * the number of x-tiles by default), cfg[5] z-march length (3-D RK3/RK4: a
  * workgroup runs cfg[5] consecutive layers of one tile column bottom to top
  * and takes each lower z-face's other side from the layer it ran before;
- * 1 = one layer per workgroup). Writes min(n, 6) entries and zeros beyond. */
+ * 1 = one layer per workgroup), cfg[6] 1-D elements per workgroup (0: a
+ * chunk per CU, the default; -1: the chunks the halo bound leaves, capacity
+ * minus both halos; k > 0: k owned elements when they fit with the halos).
+ * Writes min(n, 7) entries and zeros beyond. */
 int dg_launch_config(const dg_solver *h, int64_t *cfg, int n);
 
-/* Set the launch configuration (same layout as dg_launch_config, n = 6;
+/* Set the launch configuration (same layout as dg_launch_config, n = 7;
  * cfg[3] is ignored and the autotuned flag cleared), e.g. to reapply a
  * configuration found by dg_autotune in an earlier run. 3-D: cfg[5] in
  * 1..K[2], cfg[1] must divide the number of z-units ceil(K[2] / cfg[5]) and
  * cfg[4] the number of x-tiles; 1-D/2-D: cfg[1], cfg[4] and cfg[5] must
- * equal the values in use. cfg[0] in {0, 1}, cfg[2] in 1..1024. Every
+ * equal the values in use. cfg[0] in {0, 1}, cfg[2] in 1..1024, cfg[6] in
+ * -1..2^30 (any dimension; used by 1-D RK3/RK4 meshes split into chunks). Every
  * configuration computes the same results bit for bit. DG_EINVAL on a bad
  * entry (nothing changed), DG_ESTATE for a batch member. Takes effect at the
  * next dg_step; work already enqueued is unaffected. */

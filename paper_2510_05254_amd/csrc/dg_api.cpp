@@ -565,9 +565,10 @@ int rk6_stage(const dg_solver *h, int s, double dt, StageParams &p, ExtraIn &x)
 
 int enqueue_steps(dg_solver *h, int rk, double dt, int64_t nsteps)
 {
-    // a chunk per CU: the steps of a launch then run in one round of
-    // workgroups (chunking never changes an element's arithmetic)
-    const MsPlan pl = ms_plan(h, rk, ms_spread(h->K[0], h->cus));
+    // by default a chunk per CU: the steps of a launch then run in one round
+    // of workgroups (chunking never changes an element's arithmetic)
+    const int64_t tcap = h->ms_chunk == 0 ? ms_spread(h->K[0], h->cus) : (h->ms_chunk < 0 ? 0 : h->ms_chunk);
+    const MsPlan pl = ms_plan(h, rk, tcap);
     if (pl.ok) return step_ms(h, rk, dt, nsteps, pl);
     for (int64_t s = 0; s < nsteps; ++s) {
         const int rc = rk == DG_RK6 ? step_rk6(h, dt) : step_rk34(h, rk, dt);
@@ -944,22 +945,26 @@ int dg_autotune(dg_solver *h, int rk, double dt, int trial_steps)
     if (rc) return rc;
     if (rk == DG_RK6 && (rc = ensure_rk6(h))) return rc;
 
-    // Launch configurations (tile order, 1-D halo bound, z-slab, x-block,
-    // z-march length), searched in stages: 3-D, first tile order x x-block
-    // (one-layer units), then the z-slab, then the z-march length (RK3/RK4
-    // only: the RK6 kernel runs one layer per tile); 2-D, the tile order;
-    // 1-D chunked meshes, the halo bound. Each stage keeps the fastest of its
-    // candidates and the incumbent. Every candidate is timed for trial_steps
-    // steps from a saved copy of U (after one warm-up step), then U is
-    // restored.
-    struct Cfg { int plain, ms_div; int64_t slab, xblk, zlen; };
-    const Cfg keep = {h->plain_order, h->ms_div, h->slab, h->xblk, h->zlen};
+    // Launch configurations (tile order, 1-D halo bound and chunk length,
+    // z-slab, x-block, z-march length), searched in stages: 3-D, first tile
+    // order x x-block (one-layer units), then the z-slab, then the z-march
+    // length (RK3/RK4 only: the RK6 kernel runs one layer per tile); 2-D, the
+    // tile order; 1-D chunked meshes, the elements per workgroup (a chunk per
+    // CU, two per CU, the halo-bound plan) x the halo bound. Each stage keeps
+    // the fastest of its candidates (the defaults are among them). Every
+    // candidate is timed for trial_steps steps from a saved copy of U (after
+    // one warm-up step), then U is restored.
+    struct Cfg { int plain, ms_div; int64_t slab, xblk, zlen, chunk; };
+    const Cfg keep = {h->plain_order, h->ms_div, h->slab, h->xblk, h->zlen, h->ms_chunk};
     std::vector<std::vector<Cfg>> stages;
     const MsPlan pl = ms_plan(h, rk);
     if (pl.ok) {
         if (!pl.whole) {
             std::vector<Cfg> st;
-            for (int dv : {6, 10, 16, 24, 40}) st.push_back({h->plain_order, dv, h->slab, h->xblk, h->zlen});
+            // elements per workgroup (a chunk per CU, two per CU, the halo-bound
+            // plan) x steps per launch (the halo bound)
+            for (int64_t ch : {int64_t(0), ms_spread(h->K[0], 2 * h->cus), int64_t(-1)})
+                for (int dv : {6, 10, 16, 24, 40}) st.push_back({h->plain_order, dv, h->slab, h->xblk, h->zlen, ch});
             stages.push_back(st);
         }
     } else if (h->dim == 3) {
@@ -967,12 +972,13 @@ int dg_autotune(dg_solver *h, int rk, double dt, int trial_steps)
         for (int64_t xb = h->tiles_x; xb % 2 == 0 && xb / 2 >= 2; xb /= 2) xbs.push_back(xb / 2);
         std::vector<Cfg> s1;
         for (int plain = 0; plain <= 1; ++plain)
-            for (int64_t xb : xbs) s1.push_back({plain, h->ms_div, 1, xb, 1});
+            for (int64_t xb : xbs) s1.push_back({plain, h->ms_div, 1, xb, 1, h->ms_chunk});
         stages.push_back(s1);
         stages.push_back({});                          // z-slabs: filled from the stage-1 winner
         if (rk != DG_RK6) stages.push_back({});        // z-march lengths: filled likewise
     } else if (h->dim == 2) {
-        stages.push_back({{0, h->ms_div, h->slab, h->xblk, h->zlen}, {1, h->ms_div, h->slab, h->xblk, h->zlen}});
+        stages.push_back({{0, h->ms_div, h->slab, h->xblk, h->zlen, h->ms_chunk},
+                          {1, h->ms_div, h->slab, h->xblk, h->zlen, h->ms_chunk}});
     }
     if (stages.empty()) {
         h->tuned = 1;
@@ -997,6 +1003,7 @@ int dg_autotune(dg_solver *h, int rk, double dt, int trial_steps)
         h->slab = c.slab;
         h->xblk = c.xblk;
         h->zlen = c.zlen;
+        h->ms_chunk = c.chunk;
     };
     // time one candidate; U is restored afterwards
     auto time_cfg = [&](const Cfg &c, float &ms_t) {
@@ -1022,12 +1029,12 @@ int dg_autotune(dg_solver *h, int rk, double dt, int trial_steps)
         std::vector<Cfg> cand = stages[si];
         if (h->dim == 3 && !pl.ok && si == 1) {
             for (int64_t sl = 2; sl <= h->K[2]; sl *= 2)
-                if (h->K[2] % sl == 0) cand.push_back({best.plain, best.ms_div, sl, best.xblk, 1});
+                if (h->K[2] % sl == 0) cand.push_back({best.plain, best.ms_div, sl, best.xblk, 1, best.chunk});
         } else if (h->dim == 3 && !pl.ok && si == 2) {
             for (int64_t zl : {2, 4, 8, 16}) {
                 if (zl > h->K[2]) break;
                 const int64_t nz = (h->K[2] + zl - 1) / zl;
-                cand.push_back({best.plain, best.ms_div, nz % best.slab == 0 ? best.slab : 1, best.xblk, zl});
+                cand.push_back({best.plain, best.ms_div, nz % best.slab == 0 ? best.slab : 1, best.xblk, zl, best.chunk});
             }
         }
         for (const Cfg &c : cand) {
@@ -1054,7 +1061,7 @@ int dg_autotune(dg_solver *h, int rk, double dt, int trial_steps)
 int dg_launch_config(const dg_solver *h, int64_t *cfg, int n)
 {
     if (!h || !cfg || n < 0) return fail(DG_EINVAL, "NULL argument or n < 0");
-    const int64_t v[kLaunchCfg] = {h->plain_order, h->slab, h->ms_div, h->tuned, h->xblk, h->zlen};
+    const int64_t v[kLaunchCfg] = {h->plain_order, h->slab, h->ms_div, h->tuned, h->xblk, h->zlen, h->ms_chunk};
     for (int i = 0; i < n && i < kLaunchCfg; ++i) cfg[i] = v[i];
     for (int i = kLaunchCfg; i < n; ++i) cfg[i] = 0;
     return DG_OK;
@@ -1063,11 +1070,13 @@ int dg_launch_config(const dg_solver *h, int64_t *cfg, int n)
 int dg_set_launch_config(dg_solver *h, const int64_t *cfg, int n)
 {
     if (!h || !cfg) return fail(DG_EINVAL, "NULL argument");
-    if (n != kLaunchCfg) return fail(DG_EINVAL, "n must be 6");
+    if (n != kLaunchCfg) return fail(DG_EINVAL, "n must be 7");
     if (h->batch) return fail(DG_ESTATE, "solver belongs to a batch");
-    const int64_t plain = cfg[0], slab = cfg[1], ms_div = cfg[2], xblk = cfg[4], zlen = cfg[5];
+    const int64_t plain = cfg[0], slab = cfg[1], ms_div = cfg[2], xblk = cfg[4], zlen = cfg[5], chunk = cfg[6];
     if (plain != 0 && plain != 1) return fail(DG_EINVAL, "cfg[0] (tile order) must be 0 or 1");
     if (ms_div < 1 || ms_div > 1024) return fail(DG_EINVAL, "cfg[2] (halo-bound divisor) must be in 1..1024");
+    if (chunk < -1 || chunk > (int64_t(1) << 30))
+        return fail(DG_EINVAL, "cfg[6] (1-D chunk request) must be -1, 0 or an element count up to 2^30");
     if (h->dim == 3) {
         if (zlen < 1 || zlen > h->K[2]) return fail(DG_EINVAL, "cfg[5] (z-march length) must be in 1..K[2]");
         const int64_t nz = (h->K[2] + zlen - 1) / zlen;
@@ -1084,6 +1093,7 @@ int dg_set_launch_config(dg_solver *h, const int64_t *cfg, int n)
     h->ms_div = (int)ms_div;
     h->xblk = xblk;
     h->zlen = zlen;
+    h->ms_chunk = chunk;
     h->tuned = 0;
     return DG_OK;
 }

@@ -46,7 +46,7 @@ size_t round_up(size_t x);
 }  // namespace dg
 
 // entries of a launch configuration (dg_launch_config / dg_set_launch_config)
-constexpr int kLaunchCfg = 6;
+constexpr int kLaunchCfg = 7;
 
 struct dg_solver {
     int dim = 0, N = 0, eq = 0, prec = 0, nvar = 0, n1 = 0, np = 0;
@@ -77,6 +77,9 @@ struct dg_solver {
     // follow from the halo bound capacity / (ms_div * stages)
     int plain_order = 0;
     int ms_div = 10;
+    // 1-D chunk request: 0 one chunk per CU, -1 none (the halo-bound plan),
+    // k > 0 k owned elements per workgroup
+    int64_t ms_chunk = 0;
     int cus = 256;                  // compute units of the device
     int64_t zlen = 1;               // 3-D: layers per z-marching unit (1 = one layer per tile)
     int tuned = 0;

@@ -238,18 +238,20 @@ def dg_autotune(h, rk, dt, trial_steps=3):
     _call("dg_autotune", h, int(rk), float(dt), int(trial_steps))
 
 
-LAUNCH_CFG = 6
+LAUNCH_CFG = 7
 
 
 def dg_launch_config(h):
-    """(tile order, z-slab, 1-D halo-bound divisor, tuned flag, x-block, z-march length)."""
+    """(tile order, z-slab, 1-D halo-bound divisor, tuned flag, x-block, z-march length,
+    1-D chunk request)."""
     out = (ctypes.c_int64 * LAUNCH_CFG)()
     _call("dg_launch_config", h, out, LAUNCH_CFG)
     return tuple(int(x) for x in out)
 
 
 def dg_set_launch_config(h, cfg):
-    """Set (tile order, z-slab, 1-D halo-bound divisor, ignored, x-block, z-march length)."""
+    """Set (tile order, z-slab, 1-D halo-bound divisor, ignored, x-block, z-march length,
+    1-D chunk request)."""
     vals = [int(x) for x in cfg]
     if len(vals) != LAUNCH_CFG:
         raise ValueError(f"a launch configuration has {LAUNCH_CFG} entries")

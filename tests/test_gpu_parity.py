@@ -87,24 +87,28 @@ def test_parity_1d_chunked_multistep(N, K, eq, rk, nsteps):
 # many workgroups that each own a few elements and carry halos several times
 # wider. Launches read one state array and write the other, so a workgroup
 # never loads a halo that a neighbouring chunk has already advanced: every
-# steps-per-launch bound (and odd or even launch counts, single-step launches
-# ending in a copy launch) ends bitwise at the same state, equal to the oracle.
+# steps-per-launch bound and chunk length (a chunk per CU, the halo-bound
+# plan, a few elements, the whole mesh in one chunk; odd or even launch counts,
+# single-step launches ending in a copy launch) ends bitwise at the same state,
+# equal to the oracle.
 @pytest.mark.parametrize("N,K,eq,nsteps", [(3, 700, ADV, 25), (7, 300, ADV, 13), (2, 2000, EUL, 9), (5, 129, ADV, 1)])
 def test_1d_chunkings_bitwise(N, K, eq, nsteps):
     w, ax, U0, dt = case(1, N, (K,), eq, 31)
     ref = None
     with dg.Solver(1, N, (K,), eq, params(1, eq)) as s:
         base = s.launch_config()
-        for div in (10, 6, 24, 40, 1024):
+        assert base[6] == 0                     # a chunk per CU by default
+        for div, chunk in ((10, 0), (6, 0), (24, 0), (40, 0), (1024, 0), (10, -1), (6, 3), (16, 17), (40, K)):
             c = list(base)
-            c[2] = div
+            c[2], c[6] = div, chunk
             s.set_launch_config(c)
+            assert s.launch_config()[6] == chunk
             s.set_state(U0)
             s.step(4, dt, nsteps)
             got = s.get_state()
             if ref is None:
                 ref = got
-            np.testing.assert_array_equal(got, ref, err_msg=f"halo divisor {div}")
+            np.testing.assert_array_equal(got, ref, err_msg=f"halo divisor {div}, chunk {chunk}")
     Uo = oracle.step(1, N, (K,), eq, params(1, eq), U0, 4, dt, nsteps)
     parity(ref, Uo, what=f"1-D N={N} K={K} eq={eq} chunked")
 
@@ -361,7 +365,8 @@ def test_set_launch_config_errors():
     with dg.Solver(3, 4, (8, 3, 6), EUL, params(3, EUL)) as s:
         base = list(s.launch_config())
         assert base[4] == 4            # 8 elements, 2 per tile
-        for i, v in ((0, 2), (0, -1), (1, 4), (1, 0), (2, 0), (2, 2000), (4, 3), (4, 0), (5, 0), (5, 7)):
+        for i, v in ((0, 2), (0, -1), (1, 4), (1, 0), (2, 0), (2, 2000), (4, 3), (4, 0), (5, 0), (5, 7), (6, -2),
+                     (6, (1 << 30) + 1)):
             c = list(base)
             c[i] = v
             with pytest.raises(dg.DgError) as e:
@@ -371,7 +376,7 @@ def test_set_launch_config_errors():
         with pytest.raises(ValueError):
             s.set_launch_config(base[:4])
         with pytest.raises(dg.DgError) as e:
-            dg._call("dg_set_launch_config", s.h, (dg.ctypes.c_int64 * 6)(*base), 5)
+            dg._call("dg_set_launch_config", s.h, (dg.ctypes.c_int64 * 7)(*base), 6)
         assert e.value.status == dg.DG_EINVAL
         # the z-slab counts z-units: with chunks of 4 layers K_z = 6 has 2
         c = list(base)
