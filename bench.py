@@ -263,6 +263,62 @@ def efficiency_main(a):
                           "rel_l2_error": rel, "unknowns": w.unknowns}), flush=True)
 
 
+def size_sweep_main(a):
+    """Throughput against problem size (the paper's Sec. 3.2 finding that GPUs
+    need about 1e7 degrees of freedom): 2-D advection N = 7, RK4, FP64 on
+    K x K meshes, one solve alone and B equal solves in one batch, where B
+    brings the batch to about 4.2e6 unknowns (at most 1024 members)."""
+    import math
+    import torch
+    from paper_2510_05254_amd import dg
+    from paper_2510_05254_amd import workloads as W
+
+    torch.cuda.init()
+    N, rk = 7, 4
+    for K in (4, 8, 16, 32, 64, 128, 256, 512):
+        w = W.scaled(W.config(2), (K, K))
+        unknowns = w.unknowns
+        B = int(min(1024, max(1, math.ceil(4194304 / unknowns))))
+        stream = torch.cuda.Stream()
+        solvers = [dg.Solver(2, N, (K, K), W.ADVECTION, (1.0, 0.5), hip_stream=stream.cuda_stream)
+                   for _ in range(B)]
+        ax = solvers[0].axis_coords()
+        U0 = W.initial_state(w, ax)
+        dt, _ = W.time_step(w, ax, U0)
+        # about 50 ms of work alone at the smallest size's launch rate, at least 20 steps
+        steps = max(20, min(2000, int(2e9 / unknowns)))
+        s0 = solvers[0]
+        s0.set_state(U0)
+        s0.step(rk, dt, 2)
+        s0.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        s0.step(rk, dt, steps)
+        e1.record(stream)
+        e1.synchronize()
+        alone = e0.elapsed_time(e1) / 1e3
+        for s in solvers:
+            s.set_state(U0)
+        torch.cuda.synchronize()
+        with dg.Batch(hip_stream=stream.cuda_stream, graph=True) as b:
+            for s in solvers:
+                b.add(s, rk, dt, steps + 2)
+            b.run(2)                                  # warm-up and graph capture
+            b.synchronize()
+            e0.record(stream)
+            b.run_all()
+            e1.record(stream)
+            e1.synchronize()
+            batched = e0.elapsed_time(e1) / 1e3
+        for s in solvers:
+            s.close()
+        upd = unknowns * 4 * steps
+        print(json.dumps({"study": "throughput_vs_size_adv2d_N7", "K": [K, K], "unknowns": unknowns,
+                          "steps": steps, "alone_dof_updates_per_s": upd / alone,
+                          "batch_members": B, "batched_dof_updates_per_s": B * upd / batched,
+                          "batched_unknowns": B * unknowns}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -286,6 +342,8 @@ def main():
     ap.add_argument("--chunk", type=int, default=32)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--efficiency", action="store_true", help="error vs computing time study")
+    ap.add_argument("--size-sweep", action="store_true",
+                    help="throughput vs problem size, one solve alone and many in one batch")
     ap.add_argument("--launch-config", default=None, metavar="ORDER,SLAB,XBLOCK[,ZLEN]",
                     help="tile order (0 XCD-contiguous, 1 plain), z-slab, x-block and z-march "
                          "length (layers per workgroup) to time")
@@ -299,6 +357,9 @@ def main():
         sys.exit(2)
     if a.serve:
         serve_main(a)
+        return
+    if a.size_sweep:
+        size_sweep_main(a)
         return
     if a.efficiency:
         efficiency_main(a)

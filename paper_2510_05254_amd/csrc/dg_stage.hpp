@@ -780,28 +780,58 @@ stage_kernel_x(const StageParams p, const ExtraIn x)
     }
 }
 
+// A batch member's stage parameters (and its first virtual tile, and for the
+// fused RK6 stages its further inputs) copied into LDS by the workgroup:
+// stage_tile reads them many times, and from LDS a read is a broadcast
+// instead of a dependent global load.
+template <bool XIN>
+struct MemberLds {
+    StageParams p;
+    ExtraIn x[XIN ? 1 : 0 + 1];
+    uint32_t base;
+};
+
+template <bool XIN, int THREADS>
+__device__ __forceinline__ void load_member(const BatchLaunch &b, uint32_t s, MemberLds<XIN> &m, int tid)
+{
+    static_assert(sizeof(StageParams) % 4 == 0 && sizeof(ExtraIn) % 4 == 0, "copied as dwords");
+    constexpr int NP4 = sizeof(StageParams) / 4, NX4 = XIN ? (int)sizeof(ExtraIn) / 4 : 0;
+    static_assert(NP4 + NX4 + 1 <= THREADS, "one dword per thread");
+    if (tid < NP4) {
+        reinterpret_cast<uint32_t *>(&m.p)[tid] = reinterpret_cast<const uint32_t *>(b.params + s)[tid];
+    } else if (tid < NP4 + NX4) {
+        reinterpret_cast<uint32_t *>(&m.x[0])[tid - NP4] = reinterpret_cast<const uint32_t *>(b.extra + s)[tid - NP4];
+    } else if (tid == NP4 + NX4) {
+        m.base = b.tile_base[s];
+    }
+}
+
 // Batched stage: one launch advances every solve of one kernel class (same
 // precision, equation, dimension, degree; meshes, arrays and time steps
 // differ). Virtual tile T (XCD-contiguous numbering over all solves) belongs
 // to solve tile_solve[T] and is that solve's tile T - tile_base[solve].
-// The LDS layout and register target are the single-solve kernel's for the
-// class (stage_vel, stage_waves).
+// The LDS layout is the single-solve kernel's for the class (stage_vel; not
+// for N = 1, whose batch kernel then needs more registers than four waves
+// per SIMD leave); the register target stays at four waves per SIMD (the
+// batch's own per-tile state does not fit the six-wave budget without
+// spilling).
 template <typename real, int DIM, int N, int EQ, bool BUF, int NIN>
-__global__ void __launch_bounds__((Geo<DIM, N>::THREADS))
-__attribute__((amdgpu_waves_per_eu(stage_waves(DIM, N, EQ, (int)sizeof(real), BUF))))
+__global__ void __launch_bounds__((Geo<DIM, N>::THREADS)) __attribute__((amdgpu_waves_per_eu(4)))
 stage_kernel_batch(const BatchLaunch b)
 {
     using G = Geo<DIM, N>;
-    constexpr int W = stage_waves(DIM, N, EQ, (int)sizeof(real), BUF);
-    constexpr bool VEL = stage_vel(DIM, N, EQ, (int)sizeof(real), BUF);
+    constexpr int W = 4;
+    constexpr bool VEL = stage_vel(DIM, N, EQ, (int)sizeof(real), BUF) && N > 1;
     __shared__ StageLds<real, DIM, N, EQ, 1, VEL> lds;
+    __shared__ MemberLds<false> mem;
     const ThreadSetup<DIM, N, 1> ts;
     const real dval = ts.tid < G::N1 * G::N1 ? static_cast<const real *>(b.D)[ts.tid] : real(0);
     for (uint32_t vb = blockIdx.x; vb < b.ntiles; vb += gridDim.x) {
         const uint32_t xb = vb & (kXcds - 1), jb = vb / kXcds;
         const uint32_t T = xb * b.xq + (xb < b.xr ? xb : b.xr) + jb;
-        const uint32_t s = b.tile_solve[T];
-        stage_tile<real, DIM, N, EQ, BUF, 1, false, NIN, W, VEL>(b.params[s], T - b.tile_base[s], lds, ts, dval);
+        load_member<false, G::THREADS>(b, b.tile_solve[T], mem, ts.tid);
+        __syncthreads();
+        stage_tile<real, DIM, N, EQ, BUF, 1, false, NIN, W, VEL>(mem.p, T - mem.base, lds, ts, dval);
         __syncthreads();
     }
 }
@@ -837,13 +867,15 @@ stage_kernel_batch_x(const BatchLaunch b)
 {
     using G = Geo<DIM, N>;
     __shared__ StageLds<real, DIM, N, EQ, 1, false> lds;
+    __shared__ MemberLds<true> mem;
     const ThreadSetup<DIM, N, 1> ts;
     const real dval = ts.tid < G::N1 * G::N1 ? static_cast<const real *>(b.D)[ts.tid] : real(0);
     for (uint32_t vb = blockIdx.x; vb < b.ntiles; vb += gridDim.x) {
         const uint32_t xb = vb & (kXcds - 1), jb = vb / kXcds;
         const uint32_t T = xb * b.xq + (xb < b.xr ? xb : b.xr) + jb;
-        const uint32_t s = b.tile_solve[T];
-        stage_tile<real, DIM, N, EQ, BUF, 1, true>(b.params[s], T - b.tile_base[s], lds, ts, dval, b.extra + s);
+        load_member<true, G::THREADS>(b, b.tile_solve[T], mem, ts.tid);
+        __syncthreads();
+        stage_tile<real, DIM, N, EQ, BUF, 1, true>(mem.p, T - mem.base, lds, ts, dval, &mem.x[0]);
         __syncthreads();
     }
 }
