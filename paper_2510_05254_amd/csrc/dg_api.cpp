@@ -305,9 +305,9 @@ int setup_solver(dg_solver *h, int dim, int N, const int64_t *K, int equation, c
     h->lay = layout_for(dim, N, K, equation, precision);
     h->stage = stage_fn(precision, equation, dim, N);
     if (!h->stage) return fail(DG_ENOTSUP, "no stage kernel built for this configuration");
-    h->epb = stage_epb(dim, N);
+    h->epb = stage_epb(dim, N, equation);
     h->tiles_x = (h->K[0] + h->epb - 1) / h->epb;
-    h->epy = stage_epy(dim, N);
+    h->epy = stage_epy(dim, N, equation);
     h->tiles_y = (h->K[1] + h->epy - 1) / h->epy;
     // default 3-D tile order: x-blocks of about an eighth of the x-tiles (the
     // largest divisor in [4, max(4, tiles_x / 8)], else whole rows), walked

@@ -184,10 +184,11 @@ StageFn stage_fn(int precision, int equation, int dim, int N);
 StageXFn stage_x_fn(int precision, int equation, int dim, int N);
 BatchFn batch_fn(int precision, int equation, int dim, int N);
 BatchXFn batch_x_fn(int precision, int equation, int dim, int N);
-// Threads per block and elements per block of the stage kernel for (dim, N).
-int stage_threads(int dim, int N);
-int stage_epb(int dim, int N);
-int stage_epy(int dim, int N);
+// Threads per block, elements per tile along x and element rows per tile of
+// the stage kernel for (dim, N, equation).
+int stage_threads(int dim, int N, int eq);
+int stage_epb(int dim, int N, int eq);
+int stage_epy(int dim, int N, int eq);
 
 hipError_t launch_reduce(int precision, const ReduceParams &p, int64_t blocks, hipStream_t s);
 hipError_t launch_layout(int to_precision, int from_precision, const LayoutParams &p, hipStream_t s);

@@ -139,32 +139,33 @@ StageFn stage_fn(int precision, int equation, int dim, int N)
 }
 
 // what: 0 threads per workgroup, 1 elements per tile along x, 2 element rows
-template <int DIM>
+template <int DIM, int EQ>
 static int threads_n(int N, int what)
 {
     switch (N) {
-#define DG_CASE(n) \
-    case n: return what == 0 ? Geo<DIM, n>::THREADS : what == 1 ? Geo<DIM, n>::EPB : Geo<DIM, n>::EPY;
+#define DG_CASE(n)                                                                             \
+    case n:                                                                                    \
+        return what == 0 ? Geo<DIM, n, EQ>::THREADS : what == 1 ? Geo<DIM, n, EQ>::EPB : Geo<DIM, n, EQ>::EPY;
         DG_CASE(1) DG_CASE(2) DG_CASE(3) DG_CASE(4) DG_CASE(5) DG_CASE(6) DG_CASE(7) DG_CASE(8)
 #undef DG_CASE
     default: return 0;
     }
 }
 
-int stage_threads(int dim, int N)
+template <int EQ>
+static int geo_of(int dim, int N, int what)
 {
-    return dim == 1 ? threads_n<1>(N, 0) : dim == 2 ? threads_n<2>(N, 0) : threads_n<3>(N, 0);
+    return dim == 1 ? threads_n<1, EQ>(N, what) : dim == 2 ? threads_n<2, EQ>(N, what) : threads_n<3, EQ>(N, what);
 }
 
-int stage_epb(int dim, int N)
+static int geo_q(int dim, int N, int eq, int what)
 {
-    return dim == 1 ? threads_n<1>(N, 1) : dim == 2 ? threads_n<2>(N, 1) : threads_n<3>(N, 1);
+    return eq == 0 ? geo_of<0>(dim, N, what) : geo_of<1>(dim, N, what);     // 0: advection
 }
 
-int stage_epy(int dim, int N)
-{
-    return dim == 1 ? threads_n<1>(N, 2) : dim == 2 ? threads_n<2>(N, 2) : threads_n<3>(N, 2);
-}
+int stage_threads(int dim, int N, int eq) { return geo_q(dim, N, eq, 0); }
+int stage_epb(int dim, int N, int eq) { return geo_q(dim, N, eq, 1); }
+int stage_epy(int dim, int N, int eq) { return geo_q(dim, N, eq, 2); }
 
 static int64_t grid_for(int64_t n, int threads)
 {

@@ -84,19 +84,31 @@ constexpr bool stage_vel(int DIM, int N, int EQ, int rbytes, bool BUF)
 // tile and has its 500 face points in one pass.
 constexpr int tile_rows(int DIM, int N) { return DIM == 3 && N == 4 ? 2 : 1; }
 
+// Nodes per lane of the stage kernels: two for 2-D advection, one otherwise.
+// A 2-D advection tile moves few bytes per node and its lanes spend most of
+// the tile waiting on global loads, with the CU already at eight waves per
+// SIMD; two nodes per lane put twice the loads in flight per wave (and twice
+// the elements per workgroup) at 46-61 VGPRs, still eight waves. Euler tiles
+// (more registers per node) lose occupancy at two nodes per lane and get
+// slower. Every choice computes the same bits: a node's arithmetic does not
+// depend on the lane or the tile that holds it.
+constexpr int stage_npl(int DIM, int EQ) { return DIM == 2 && EQ == 0 ? 2 : 1; }
+
 // A tile is EPB elements along x times EPY along y; TM scales it along x:
-// EPB = max(1, 256 TM / (N+1)^dim).
-template <int DIM, int N, int TM = 1>
+// EPB = max(1, 256 TM NPL / (N+1)^dim), and THREADS lanes of NPL nodes cover
+// it (lane t holds tile nodes t, t + THREADS, ...).
+template <int DIM, int N, int EQ, int TM = 1>
 struct Geo {
     static constexpr int N1 = N + 1;
     static constexpr int NP = ipow(N1, DIM);          // nodes per element
     static constexpr int NF1 = ipow(N1, DIM - 1);     // nodes per face
-    static constexpr int EPB = (256 * TM / NP) < 1 ? 1 : (256 * TM / NP);
+    static constexpr int NPL = stage_npl(DIM, EQ);     // nodes per lane
+    static constexpr int EPB = (256 * TM * NPL / NP) < 1 ? 1 : (256 * TM * NPL / NP);
     static constexpr int EPY = tile_rows(DIM, N);
     static_assert(EPY == 1 || EPY == 2, "the face table encodes one bit of tile row");
     static constexpr int NS = EPB * EPY;              // element slots, slot = sx + EPB sy
     static constexpr int TN = NS * NP;
-    static constexpr int THREADS = ((TN + 63) / 64) * 64;
+    static constexpr int THREADS = (((TN + NPL - 1) / NPL + 63) / 64) * 64;
     static constexpr int NFX = EPY * (EPB + 1) * NF1;                 // x-plane points
     static constexpr int NFY = DIM > 1 ? EPB * (EPY + 1) * NF1 : 0;   // y-plane points
     static constexpr int NFZ = DIM > 2 ? NS * 2 * NF1 : 0;            // z-face points
@@ -253,7 +265,7 @@ struct Arr<real, false> {
 // from them with the same operations, so the results are the same bits).
 template <typename real, int DIM, int N, int EQ, int TM, bool VEL, bool ZM = false>
 struct StageLds {
-    using G = Geo<DIM, N, TM>;
+    using G = Geo<DIM, N, EQ, TM>;
     static constexpr int NV = Vars<EQ, DIM>::NV, NSYM = Vars<EQ, DIM>::NSYM;
     static constexpr int NE = EQ == 0 ? 1 : (VEL ? DIM : NSYM + 1);
     real sY[NV][G::TN];
@@ -275,28 +287,34 @@ template <typename real, int DIM, int N, int EQ, int TM, bool VEL, int WAVES>
 constexpr bool stage_zm()
 {
     constexpr long lds = 160 * 1024;
-    constexpr long wg_waves = Geo<DIM, N, TM>::THREADS / 64;
+    constexpr long wg_waves = Geo<DIM, N, EQ, TM>::THREADS / 64;
     constexpr long cap = 4 * WAVES / wg_waves;
     constexpr long with = lds / (long)sizeof(StageLds<real, DIM, N, EQ, TM, VEL, true>);
     constexpr long without = lds / (long)sizeof(StageLds<real, DIM, N, EQ, TM, VEL, false>);
     return DIM == 3 && (with < cap ? with : cap) == (without < cap ? without : cap);
 }
 
-// per-thread constants of a workgroup (independent of the tile)
-template <int DIM, int N, int TM>
+// per-thread constants of a workgroup (independent of the tile), for each
+// of the lane's nodes
+template <int DIM, int N, int EQ, int TM>
 struct ThreadSetup {
-    int tid, slot, sx, sy, n, ijk[3];
+    static constexpr int NPL = Geo<DIM, N, EQ, TM>::NPL;
+    int tid, slot[NPL], sx[NPL], sy[NPL], n[NPL], ijk[NPL][3];
     __device__ __forceinline__ ThreadSetup()
     {
-        using G = Geo<DIM, N, TM>;
+        using G = Geo<DIM, N, EQ, TM>;
         tid = threadIdx.x;
-        slot = tid / G::NP;
-        sy = slot / G::EPB;
-        sx = slot - sy * G::EPB;
-        n = tid - slot * G::NP;
-        ijk[0] = n % G::N1;
-        ijk[1] = DIM > 1 ? (n / G::N1) % G::N1 : 0;
-        ijk[2] = DIM > 2 ? n / (G::N1 * G::N1) : 0;
+#pragma unroll
+        for (int u = 0; u < NPL; ++u) {
+            const int vt = tid + u * G::THREADS;
+            slot[u] = vt / G::NP;
+            sy[u] = slot[u] / G::EPB;
+            sx[u] = slot[u] - sy[u] * G::EPB;
+            n[u] = vt - slot[u] * G::NP;
+            ijk[u][0] = n[u] % G::N1;
+            ijk[u][1] = DIM > 1 ? (n[u] / G::N1) % G::N1 : 0;
+            ijk[u][2] = DIM > 2 ? n[u] / (G::N1 * G::N1) : 0;
+        }
     }
 };
 
@@ -338,10 +356,10 @@ template <typename real, int DIM, int N, int EQ, bool BUF, int TM, bool XIN = fa
           int WAVES = 4, bool VEL = false, bool ZM = false>
 __device__ __forceinline__ void stage_tile_at(const StageParams &p, int64_t tx, int64_t ty, int64_t ez,
                                               bool zl, StageLds<real, DIM, N, EQ, TM, VEL, ZM> &lds,
-                                              const ThreadSetup<DIM, N, TM> &ts, real dval,
+                                              const ThreadSetup<DIM, N, EQ, TM> &ts, real dval,
                                               const ExtraIn *x = nullptr)
 {
-    using G = Geo<DIM, N, TM>;
+    using G = Geo<DIM, N, EQ, TM>;
     constexpr int N1 = G::N1, NP = G::NP, NF1 = G::NF1, EPB = G::EPB, EPY = G::EPY, NS = G::NS;
     constexpr int THREADS = G::THREADS, NF = G::NF;
     constexpr int NV = Vars<EQ, DIM>::NV;
@@ -354,8 +372,8 @@ __device__ __forceinline__ void stage_tile_at(const StageParams &p, int64_t tx, 
     constexpr int NSYM = Vars<EQ, DIM>::NSYM;
     auto &sL = lds.sL;
     auto &sD = lds.sD;
-    const int tid = ts.tid, slot = ts.slot, n = ts.n;
-    const int *ijk = ts.ijk;
+    constexpr int NPL = G::NPL;
+    const int tid = ts.tid;
 
     const A yin(p.yin, p.stride, NV, NP);
     real par[3], rdx2[3];
@@ -433,10 +451,17 @@ __device__ __forceinline__ void stage_tile_at(const StageParams &p, int64_t tx, 
 
     // ---- phase 1: state, 1/rho and flux tensor into LDS; the outside trace
     // of this thread's first face point is prefetched behind the own state.
-    const bool active = EPY == 1 ? slot < nact : ts.sx < nact && ts.sy < nacty;
-    const int ln = slot * NP + n;
-    const idx_t gi = EPY == 1 ? idx_t((ebase + ex0 + slot) * ES + n)
-                              : idx_t((ebase + K0 * ts.sy + ex0 + ts.sx) * ES + n);
+    bool active[NPL];
+    int ln[NPL];
+    idx_t gi[NPL];
+#pragma unroll
+    for (int u = 0; u < NPL; ++u) {
+        const int slot = ts.slot[u], n = ts.n[u];
+        active[u] = EPY == 1 ? slot < nact : ts.sx[u] < nact && ts.sy[u] < nacty;
+        ln[u] = slot * NP + n;
+        gi[u] = EPY == 1 ? idx_t((ebase + ex0 + slot) * ES + n)
+                         : idx_t((ebase + K0 * ts.sy[u] + ex0 + ts.sx[u]) * ES + n);
+    }
     // both groups are loaded unconditionally (inactive lanes read node 0) so
     // the wait before the LDS stores covers only the first group
     // Issue order matters (vector loads retire in order): this thread's first
@@ -460,10 +485,14 @@ __device__ __forceinline__ void stage_tile_at(const StageParams &p, int64_t tx, 
         fx2 = p.ftab[4 * (tid + THREADS) + 2];
         fx3 = p.ftab[4 * (tid + THREADS) + 3];
     }
-    real y[NV], g[NV];
-    const idx_t gy = active ? gi : idx_t(0);
+    real y[NPL][NV], g[NV];
+    idx_t gy[NPL];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) y[v] = yin.ld(v, gy);
+    for (int u = 0; u < NPL; ++u) {
+        gy[u] = active[u] ? gi[u] : idx_t(0);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) y[u][v] = yin.ld(v, gy[u]);
+    }
     const bool pre = tid < NF && face_valid(fw0) && other_outside(fw0) && !z_in_lds(fw0);
     const idx_t gn0 = pre ? outside_node(fw0, fw2) : idx_t(0);
 #pragma unroll
@@ -479,39 +508,47 @@ __device__ __forceinline__ void stage_tile_at(const StageParams &p, int64_t tx, 
     // not cover them. Kernels built for six waves per SIMD load them in
     // phase 3 instead, so they are not held in registers across the phases.
     constexpr bool EARLY = NIN >= 0 && WAVES == 4;
-    real a0[NV], a1[NV];
+    real a0[NPL][NV], a1[NPL][NV];
     if constexpr (EARLY && NIN >= 1) {
         const A in0(p.in0, p.stride, NV, NP);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) a0[v] = in0.ld(v, gy);
+        for (int u = 0; u < NPL; ++u)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) a0[u][v] = in0.ld(v, gy[u]);
     }
     if constexpr (EARLY && NIN >= 2) {
         const A in1(p.in1, p.stride, NV, NP);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) a1[v] = in1.ld(v, gy);
+        for (int u = 0; u < NPL; ++u)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) a1[u][v] = in1.ld(v, gy[u]);
     }
     const bool has0 = NIN < 0 ? p.nin > 0 : NIN >= 1;
     const bool has1 = NIN < 0 ? p.nin > 1 : NIN >= 2;
     // D (loaded at kernel entry into dval, stored here so the entry does not
     // wait for it before the tile's loads are issued)
     if (tid < N1 * N1) sD[tid] = dval;
-    if (active) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) sY[v][ln] = y[v];
+    for (int u = 0; u < NPL; ++u) {
+        if (!active[u]) continue;
+        const real *yu = y[u];
+        const int lnu = ln[u];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sY[v][lnu] = yu[v];
         if constexpr (EQ == 1) {
-            const real rinv = recip(y[0]);
+            const real rinv = recip(yu[0]);
             if constexpr (VEL) {
                 // m_b (1/rho) as sym_flux and wave_speed form it; the tensor
                 // entries are rebuilt from these where they are needed
 #pragma unroll
-                for (int k = 0; k < DIM; ++k) sE[k][ln] = y[1 + k] * rinv;
+                for (int k = 0; k < DIM; ++k) sE[k][lnu] = yu[1 + k] * rinv;
             } else {
-                sE[NSYM][ln] = rinv;
+                sE[NSYM][lnu] = rinv;
 #pragma unroll
                 for (int a = 0; a < DIM; ++a)
 #pragma unroll
                     for (int b = a; b < DIM; ++b)
-                        sE[sym_index(a, b, DIM)][ln] = sym_flux(y[1 + a], y[1 + b], y[0], rinv, c2, a == b);
+                        sE[sym_index(a, b, DIM)][lnu] = sym_flux(yu[1 + a], yu[1 + b], yu[0], rinv, c2, a == b);
             }
         }
     }
@@ -610,7 +647,11 @@ __device__ __forceinline__ void stage_tile_at(const StageParams &p, int64_t tx, 
     __syncthreads();
 
     // ---- phase 3: volume term + lifts, RK stage combination, store
-    if (active) {
+#pragma unroll
+    for (int u = 0; u < NPL; ++u) {
+        if (!active[u]) continue;
+        const int slot = ts.slot[u], n = ts.n[u];
+        const int *ijk = ts.ijk[u];
         real R[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) R[v] = real(0);
@@ -660,18 +701,18 @@ __device__ __forceinline__ void stage_tile_at(const StageParams &p, int64_t tx, 
             // this layer's upper z-face state, for the next layer's lower faces
             if (ijk[2] == N) {
 #pragma unroll
-                for (int v = 0; v < NV; ++v) lds.sZ[v][slot * NF1 + ijk[0] + N1 * ijk[1]] = y[v];
+                for (int v = 0; v < NV; ++v) lds.sZ[v][slot * NF1 + ijk[0] + N1 * ijk[1]] = y[u][v];
             }
         }
         if (!EARLY && has0) {
             const A in0(p.in0, p.stride, NV, NP);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) a0[v] = in0.ld(v, gi);
+            for (int v = 0; v < NV; ++v) a0[u][v] = in0.ld(v, gi[u]);
         }
         if (!EARLY && has1) {
             const A in1(p.in1, p.stride, NV, NP);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) a1[v] = in1.ld(v, gi);
+            for (int v = 0; v < NV; ++v) a1[u][v] = in1.ld(v, gi[u]);
         }
 #pragma unroll
         for (int o = 0; o < 2; ++o) {
@@ -686,29 +727,29 @@ __device__ __forceinline__ void stage_tile_at(const StageParams &p, int64_t tx, 
                 if constexpr (!XIN) {
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
-                        real val = cy * y[v];
-                        if (has0) val = fmadd(c0, a0[v], val);
-                        if (has1) val = fmadd(c1, a1[v], val);
-                        out.st(v, gi, fmadd(cr, R[v], val));
+                        real val = cy * y[u][v];
+                        if (has0) val = fmadd(c0, a0[u][v], val);
+                        if (has1) val = fmadd(c1, a1[u][v], val);
+                        out.st(v, gi[u], fmadd(cr, R[v], val));
                     }
                 } else {
                     // fused RK6 stages: also the stored k's with nonzero weights
                     real val[NV];
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
-                        val[v] = cy * y[v];
-                        if (has0) val[v] = fmadd(c0, a0[v], val[v]);
-                        if (has1) val[v] = fmadd(c1, a1[v], val[v]);
+                        val[v] = cy * y[u][v];
+                        if (has0) val[v] = fmadd(c0, a0[u][v], val[v]);
+                        if (has1) val[v] = fmadd(c1, a1[u][v], val[v]);
                     }
                     for (int j = 0; j < x->n; ++j) {
                         if (x->c[o][j] == 0.0) continue;
                         const real cj = real(x->c[o][j]);
                         const A in(x->in[j], p.stride, NV, NP);
 #pragma unroll
-                        for (int v = 0; v < NV; ++v) val[v] = fmadd(cj, in.ld(v, gi), val[v]);
+                        for (int v = 0; v < NV; ++v) val[v] = fmadd(cj, in.ld(v, gi[u]), val[v]);
                     }
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) out.st(v, gi, fmadd(cr, R[v], val[v]));
+                    for (int v = 0; v < NV; ++v) out.st(v, gi[u], fmadd(cr, R[v], val[v]));
                 }
             }
         }
@@ -720,7 +761,7 @@ template <typename real, int DIM, int N, int EQ, bool BUF, int TM, bool XIN = fa
           int WAVES = 4, bool VEL = false>
 __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
                                            StageLds<real, DIM, N, EQ, TM, VEL> &lds,
-                                           const ThreadSetup<DIM, N, TM> &ts, real dval,
+                                           const ThreadSetup<DIM, N, EQ, TM> &ts, real dval,
                                            const ExtraIn *x = nullptr)
 {
     int64_t tx, ty, ez;
@@ -735,16 +776,16 @@ __device__ __forceinline__ void stage_tile(const StageParams &p, uint32_t L,
 // the lower z-faces' other side of every layer after the chunk's first from
 // the LDS copy of the layer below.
 template <typename real, int DIM, int N, int EQ, bool BUF, int NIN, int TM = 1>
-__global__ void __launch_bounds__((Geo<DIM, N, TM>::THREADS))
+__global__ void __launch_bounds__((Geo<DIM, N, EQ, TM>::THREADS))
 __attribute__((amdgpu_waves_per_eu(stage_waves(DIM, N, EQ, (int)sizeof(real), BUF))))
 stage_kernel(const StageParams p)
 {
-    using G = Geo<DIM, N, TM>;
+    using G = Geo<DIM, N, EQ, TM>;
     constexpr int W = stage_waves(DIM, N, EQ, (int)sizeof(real), BUF);
     constexpr bool VEL = stage_vel(DIM, N, EQ, (int)sizeof(real), BUF);
     constexpr bool ZM = stage_zm<real, DIM, N, EQ, TM, VEL, W>();
     __shared__ StageLds<real, DIM, N, EQ, TM, VEL, ZM> lds;
-    const ThreadSetup<DIM, N, TM> ts;
+    const ThreadSetup<DIM, N, EQ, TM> ts;
     const real dval = ts.tid < G::N1 * G::N1 ? static_cast<const real *>(p.D)[ts.tid] : real(0);
     for (uint32_t vb = blockIdx.x; vb < p.ntiles32; vb += gridDim.x) {
         const uint32_t xb = vb & (kXcds - 1), jb = vb / kXcds;
@@ -765,12 +806,12 @@ stage_kernel(const StageParams p)
 
 // Single-solve stage kernel with further inputs (fused RK6 stages).
 template <typename real, int DIM, int N, int EQ, bool BUF>
-__global__ void __launch_bounds__((Geo<DIM, N>::THREADS)) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__((Geo<DIM, N, EQ>::THREADS)) __attribute__((amdgpu_waves_per_eu(4)))
 stage_kernel_x(const StageParams p, const ExtraIn x)
 {
-    using G = Geo<DIM, N>;
+    using G = Geo<DIM, N, EQ>;
     __shared__ StageLds<real, DIM, N, EQ, 1, false> lds;
-    const ThreadSetup<DIM, N, 1> ts;
+    const ThreadSetup<DIM, N, EQ, 1> ts;
     const real dval = ts.tid < G::N1 * G::N1 ? static_cast<const real *>(p.D)[ts.tid] : real(0);
     for (uint32_t vb = blockIdx.x; vb < p.ntiles32; vb += gridDim.x) {
         const uint32_t xb = vb & (kXcds - 1), jb = vb / kXcds;
@@ -816,15 +857,15 @@ __device__ __forceinline__ void load_member(const BatchLaunch &b, uint32_t s, Me
 // batch's own per-tile state does not fit the six-wave budget without
 // spilling).
 template <typename real, int DIM, int N, int EQ, bool BUF, int NIN>
-__global__ void __launch_bounds__((Geo<DIM, N>::THREADS)) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__((Geo<DIM, N, EQ>::THREADS)) __attribute__((amdgpu_waves_per_eu(4)))
 stage_kernel_batch(const BatchLaunch b)
 {
-    using G = Geo<DIM, N>;
+    using G = Geo<DIM, N, EQ>;
     constexpr int W = 4;
     constexpr bool VEL = stage_vel(DIM, N, EQ, (int)sizeof(real), BUF) && N > 1;
     __shared__ StageLds<real, DIM, N, EQ, 1, VEL> lds;
     __shared__ MemberLds<false> mem;
-    const ThreadSetup<DIM, N, 1> ts;
+    const ThreadSetup<DIM, N, EQ, 1> ts;
     const real dval = ts.tid < G::N1 * G::N1 ? static_cast<const real *>(b.D)[ts.tid] : real(0);
     for (uint32_t vb = blockIdx.x; vb < b.ntiles; vb += gridDim.x) {
         const uint32_t xb = vb & (kXcds - 1), jb = vb / kXcds;
@@ -839,7 +880,7 @@ stage_kernel_batch(const BatchLaunch b)
 template <typename real, int DIM, int N, int EQ, bool BUF>
 void launch_stage_nin(const StageParams &p, int64_t grid, hipStream_t s)
 {
-    const dim3 g((unsigned)grid), b(Geo<DIM, N>::THREADS);
+    const dim3 g((unsigned)grid), b(Geo<DIM, N, EQ>::THREADS);
     switch (p.nin) {
     case 0: hipLaunchKernelGGL((stage_kernel<real, DIM, N, EQ, BUF, 0>), g, b, 0, s, p); break;
     case 1: hipLaunchKernelGGL((stage_kernel<real, DIM, N, EQ, BUF, 1>), g, b, 0, s, p); break;
@@ -862,13 +903,13 @@ hipError_t launch_stage(const StageParams &p, int64_t grid, hipStream_t s)
 // Batched fused RK6 stage: stage_kernel_x's body per member, the member's
 // further inputs from b.extra.
 template <typename real, int DIM, int N, int EQ, bool BUF>
-__global__ void __launch_bounds__((Geo<DIM, N>::THREADS)) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__((Geo<DIM, N, EQ>::THREADS)) __attribute__((amdgpu_waves_per_eu(4)))
 stage_kernel_batch_x(const BatchLaunch b)
 {
-    using G = Geo<DIM, N>;
+    using G = Geo<DIM, N, EQ>;
     __shared__ StageLds<real, DIM, N, EQ, 1, false> lds;
     __shared__ MemberLds<true> mem;
-    const ThreadSetup<DIM, N, 1> ts;
+    const ThreadSetup<DIM, N, EQ, 1> ts;
     const real dval = ts.tid < G::N1 * G::N1 ? static_cast<const real *>(b.D)[ts.tid] : real(0);
     for (uint32_t vb = blockIdx.x; vb < b.ntiles; vb += gridDim.x) {
         const uint32_t xb = vb & (kXcds - 1), jb = vb / kXcds;
@@ -883,7 +924,7 @@ stage_kernel_batch_x(const BatchLaunch b)
 template <typename real, int DIM, int N, int EQ>
 hipError_t launch_stage_batch_x(const BatchLaunch &b, bool buf, int64_t grid, hipStream_t s)
 {
-    const dim3 g((unsigned)grid), t(Geo<DIM, N>::THREADS);
+    const dim3 g((unsigned)grid), t(Geo<DIM, N, EQ>::THREADS);
     if (buf)
         hipLaunchKernelGGL((stage_kernel_batch_x<real, DIM, N, EQ, true>), g, t, 0, s, b);
     else
@@ -894,7 +935,7 @@ hipError_t launch_stage_batch_x(const BatchLaunch &b, bool buf, int64_t grid, hi
 template <typename real, int DIM, int N, int EQ, bool BUF>
 void launch_stage_batch_nin(const BatchLaunch &b, int nin, int64_t grid, hipStream_t s)
 {
-    const dim3 g((unsigned)grid), t(Geo<DIM, N>::THREADS);
+    const dim3 g((unsigned)grid), t(Geo<DIM, N, EQ>::THREADS);
     switch (nin) {
     case 0: hipLaunchKernelGGL((stage_kernel_batch<real, DIM, N, EQ, BUF, 0>), g, t, 0, s, b); break;
     case 1: hipLaunchKernelGGL((stage_kernel_batch<real, DIM, N, EQ, BUF, 1>), g, t, 0, s, b); break;
@@ -919,10 +960,10 @@ hipError_t launch_stage_x(const StageParams &p, const ExtraIn &x, int64_t grid, 
     const int64_t bytes = p.stride * Vars<EQ, DIM>::NV * (int64_t)sizeof(real);
     if (bytes < (int64_t(1) << 31))
         hipLaunchKernelGGL((stage_kernel_x<real, DIM, N, EQ, true>), dim3((unsigned)grid),
-                           dim3(Geo<DIM, N>::THREADS), 0, s, p, x);
+                           dim3(Geo<DIM, N, EQ>::THREADS), 0, s, p, x);
     else
         hipLaunchKernelGGL((stage_kernel_x<real, DIM, N, EQ, false>), dim3((unsigned)grid),
-                           dim3(Geo<DIM, N>::THREADS), 0, s, p, x);
+                           dim3(Geo<DIM, N, EQ>::THREADS), 0, s, p, x);
     return hipGetLastError();
 }
 

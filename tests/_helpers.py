@@ -21,14 +21,16 @@ PARITY_RTOL = 1e-12          # FP64 GPU vs oracle, relative L2 per variable
 ELEM_C = 1.0
 
 
-def epb(dim, N):
-    """Elements per workgroup tile the stage kernel uses (mesh choice only)."""
-    return max(1, 256 // (N + 1) ** dim)
+def epb(dim, N, eq):
+    """Elements per workgroup tile the stage kernel uses (mesh choice only):
+    256 lanes of two nodes for 2-D advection, of one node otherwise."""
+    npl = 2 if dim == 2 and eq == ADV else 1
+    return max(1, 256 * npl // (N + 1) ** dim)
 
 
-def ragged_K(dim, N):
+def ragged_K(dim, N, eq):
     """A small mesh with several x-tiles, a ragged last tile and K_y != K_z."""
-    e = epb(dim, N)
+    e = epb(dim, N, eq)
     if dim == 1:
         return (e + 3,)
     if dim == 2:

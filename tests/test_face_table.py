@@ -65,9 +65,11 @@ def dump(tmp_path_factory):
     return table
 
 
-def tile_shape(dim, N):
-    """(elements along x, rows along y) of the kernel's tile: Geo::EPB, tile_rows."""
-    epb = max(1, 256 // (N + 1) ** dim)
+def tile_shape(dim, N, nv):
+    """(elements along x, rows along y) of the kernel's tile: Geo::EPB, tile_rows
+    (2-D advection, nv = 1: lanes of two nodes, twice the elements)."""
+    npl = 2 if dim == 2 and nv == 1 else 1
+    epb = max(1, 256 * npl // (N + 1) ** dim)
     return epb, 2 if (dim == 3 and N == 4) else 1
 
 
@@ -167,12 +169,12 @@ def meshes(dim, epb, epy):
 
 @pytest.mark.parametrize("dim,N", [(d, n) for d in (1, 2, 3) for n in range(1, 9)])
 def test_kernel_tile_tables(dump, dim, N):
-    epb, epy = tile_shape(dim, N)
-    if dim == 3 and N >= 5:
-        meshes_ = [(1, 1, 1), (2, 3, 2), (3, 1, 2)]        # keep the emulation small
-    else:
-        meshes_ = meshes(dim, epb, epy)
     for nv in (1, 1 + dim):                                 # advection, isothermal Euler
+        epb, epy = tile_shape(dim, N, nv)
+        if dim == 3 and N >= 5:
+            meshes_ = [(1, 1, 1), (2, 3, 2), (3, 1, 2)]    # keep the emulation small
+        else:
+            meshes_ = meshes(dim, epb, epy)
         tab = dump(dim, N, epb, epy, nv)
         for K in meshes_:
             emulate(tab, dim, N, K, epb, epy, nv)
@@ -191,7 +193,8 @@ def test_other_tile_shapes(dump, dim, N, epb, epy, K):
 
 def test_table_sizes(dump):
     # x-planes per row, y-planes per column, z-faces per slot
-    for dim, N, epb, epy in [(1, 3, 64, 1), (2, 7, 4, 1), (3, 4, 2, 2), (3, 1, 32, 1), (2, 3, 16, 2)]:
+    for dim, N, epb, epy in [(1, 3, 64, 1), (2, 7, 4, 1), (2, 7, 8, 1), (2, 1, 128, 1), (3, 4, 2, 2),
+                             (3, 1, 32, 1), (2, 3, 16, 2)]:
         nf1 = (N + 1) ** (dim - 1)
         want = epy * (epb + 1) * nf1 + (epb * (epy + 1) * nf1 if dim > 1 else 0) + \
             (epb * epy * 2 * nf1 if dim > 2 else 0)
@@ -202,6 +205,6 @@ def test_table_sizes(dump):
 def test_emulation_rejects_a_table_for_another_layout(dump):
     """The y/z outside offsets depend on the values per element: a table built
     for one variable, read with the Euler layout's element stride, must fail."""
-    epb, epy = tile_shape(3, 4)
+    epb, epy = tile_shape(3, 4, 4)
     with pytest.raises(AssertionError):
         emulate(dump(3, 4, epb, epy, 1), 3, 4, (epb + 1, 3, 2), epb, epy, 4)

@@ -30,7 +30,7 @@ def _run_both(dim, N, K, eq, rk, nsteps, seed=1234):
 
 @pytest.mark.parametrize("dim,N,eq", ALL)
 def test_parity_rk4(dim, N, eq):
-    K = ragged_K(dim, N)
+    K = ragged_K(dim, N, eq)
     U0, Ug, Uo = _run_both(dim, N, K, eq, 4, 3)
     parity(Ug, Uo, what=f"dim={dim} N={N} eq={eq} K={K}")
     assert rel_l2_per_var(Uo, U0).max() > 1e3 * PARITY_RTOL     # the state really moved
@@ -39,7 +39,7 @@ def test_parity_rk4(dim, N, eq):
 @pytest.mark.parametrize("rk", [3, 6])
 @pytest.mark.parametrize("dim,N,eq", ALL)
 def test_parity_rk3_rk6(dim, N, eq, rk):
-    K = ragged_K(dim, N)
+    K = ragged_K(dim, N, eq)
     U0, Ug, Uo = _run_both(dim, N, K, eq, rk, 3)
     parity(Ug, Uo, what=f"rk={rk} dim={dim} N={N} eq={eq}")
     assert rel_l2_per_var(Uo, U0).max() > 1e3 * PARITY_RTOL
@@ -132,7 +132,7 @@ def test_parity_1d_whole_mesh_many_steps():
 
 @pytest.mark.parametrize("dim,N,eq", [(1, 5, EUL), (2, 3, EUL), (3, 4, EUL), (3, 2, ADV)])
 def test_conservation_and_determinism(dim, N, eq):
-    K = ragged_K(dim, N)
+    K = ragged_K(dim, N, eq)
     w, ax, U0, dt = case(dim, N, K, eq)
     with dg.Solver(dim, N, K, eq, params(dim, eq)) as s:
         s.set_state(U0)
@@ -270,7 +270,7 @@ def test_workspace_too_small_for_rk6():
 @pytest.mark.parametrize("dim,N,eq", [(1, 3, ADV), (2, 7, ADV), (2, 3, EUL), (3, 4, EUL), (3, 8, EUL)])
 def test_fp32_against_fp64_oracle(dim, N, eq):
     """FP32 state/RHS path: error against the FP64 oracle after 3 RK4 steps."""
-    K = ragged_K(dim, N)
+    K = ragged_K(dim, N, eq)
     w, ax, U0, dt = case(dim, N, K, eq)
     with dg.Solver(dim, N, K, eq, params(dim, eq), precision=dg.DG_FP32) as s:
         s.set_state(U0)
