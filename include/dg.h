@@ -227,7 +227,8 @@ void *dg_stream(const dg_solver *h);
 int dg_autotune(dg_solver *h, int rk, double dt, int trial_steps);
 
 /* The launch configuration in use: cfg[0] tile order (0 XCD-contiguous,
- * 1 plain), cfg[1] z-slab size (z-units visited together), cfg[2] 1-D
+ * 1 plain; by default plain for 2-D meshes whose x-tile count is a
+ * multiple of 8, XCD-contiguous otherwise), cfg[1] z-slab size (z-units visited together), cfg[2] 1-D
  * halo-bound divisor (steps per launch at most capacity / (cfg[2] * stages),
  * default 10; a mesh split into one chunk per CU lowers it further until
  * the chunk and its halos fit),

@@ -323,6 +323,13 @@ int setup_solver(dg_solver *h, int dim, int N, const int64_t *K, int equation, c
         // per launch on 64^3 N = 4, where FP64 is fastest with one layer)
         if (precision == DG_FP32) h->zlen = std::min<int64_t>(4, h->K[2]);
     }
+    // default 2-D tile order: plain when the x-tile count is a multiple of
+    // the XCD count (tile L runs on XCD L mod 8, so every XCD holds whole
+    // columns of tiles and meets a tile's y-neighbours one row apart, while
+    // the eight XCDs sweep the same band of rows): -6.8 % per launch on 2-D
+    // Euler 512^2 N = 3, unchanged on 2-D advection 256^2 N = 7; otherwise
+    // XCD-contiguous ranges of tiles
+    if (dim == 2 && h->tiles_x % kXcds == 0) h->plain_order = 1;
     h->ntiles = h->tiles_x * h->tiles_y * h->K[2];
     h->grid = std::min<int64_t>(h->ntiles, kMaxGrid);
     return DG_OK;
