@@ -52,7 +52,6 @@ Prints one JSON line per run.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -74,14 +73,13 @@ STAGES = {4: 4, 3: 3, 6: 7}
 STAGE_MIX = {4: [(1, 1), (2, 2), (3, 2), (2, 1)], 3: [(1, 2), (2, 1), (2, 1)],
              6: [(2, 2), (3, 2), (3, 2), (3, 2), (3, 2), (3, 2), (3, 1)]}
 assert all(sum(r + w for r, w in m) == PASSES_PER_STEP[k] or k == 6 for k, m in STAGE_MIX.items())
-KERNEL_SOURCES = ["paper_2510_05254_amd/csrc/dg_stage.hpp"]
 
 
 def kernel_hash() -> str:
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        h.update(open(os.path.join(ROOT, f), "rb").read())
-    return h.hexdigest()[:16]
+    """The stage-kernel source hash the traffic records are tied to (comments
+    excluded), as paper_2510_05254_amd.traffic computes it."""
+    from paper_2510_05254_amd.traffic import kernel_hash as h
+    return h()
 
 
 def load_traffic(workload: str, precision: str, rk: int, launch_cfg):

@@ -88,10 +88,11 @@ constexpr int tile_rows(int DIM, int N) { return DIM == 3 && N == 4 ? 2 : 1; }
 // A 2-D advection tile moves few bytes per node and its lanes spend most of
 // the tile waiting on global loads, with the CU already at eight waves per
 // SIMD; two nodes per lane put twice the loads in flight per wave (and twice
-// the elements per workgroup) at 46-61 VGPRs, still eight waves. Euler tiles
-// (more registers per node) lose occupancy at two nodes per lane and get
-// slower. Every choice computes the same bits: a node's arithmetic does not
-// depend on the lane or the tile that holds it.
+// the elements per workgroup) for 46-78 VGPRs: still eight waves at N >= 6,
+// six to eight below, where the gain is smaller. Euler tiles (more registers
+// per node) lose occupancy at two nodes per lane and get slower. Every choice
+// computes the same bits: a node's arithmetic does not depend on the lane or
+// the tile that holds it.
 constexpr int stage_npl(int DIM, int EQ) { return DIM == 2 && EQ == 0 ? 2 : 1; }
 
 // A tile is EPB elements along x times EPY along y; TM scales it along x:

@@ -9,8 +9,9 @@ FETCH_SIZE` and `rocprofv3 --pmc WRITE_SIZE` over the same bench.py command.
 The raw counters are scaled by what they read for bench.py's own calibration
 copies in the same run (device-to-device copies of exactly 2 GiB, the largest
 copyBuffer dispatches), so bytes = counter * (2 GiB / counter of the copy).
-The output records the source hash of the stage kernel so bench.py drops it
-once the kernel changes.
+The output records the hash of the stage kernel's source with its comments
+removed (code_only), so bench.py drops the record once the code changes and
+keeps it across comment edits.
 """
 from __future__ import annotations
 
@@ -26,10 +27,37 @@ COPY_BYTES = 1 << 31                  # bench.py: torch.empty(1 << 28, float64)
 KERNEL_SOURCES = ["paper_2510_05254_amd/csrc/dg_stage.hpp"]
 
 
+def code_only(text: str) -> str:
+    """C++ source without its comments, trailing blanks and empty lines: what
+    the compiler reads, so that editing a comment keeps recorded counters
+    valid while any change to the code itself does not."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in "\"'":                       # string or character literal
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            while i < n and text[i] != "\n":
+                i += 1
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+        else:
+            out.append(c)
+            i += 1
+    lines = ("".join(out)).split("\n")
+    return "\n".join(line.rstrip() for line in lines if line.strip())
+
+
 def kernel_hash() -> str:
+    """Hash of the stage-kernel sources, comments excluded (code_only)."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        h.update(open(os.path.join(ROOT, f), "rb").read())
+        h.update(code_only(open(os.path.join(ROOT, f), encoding="utf-8").read()).encode())
     return h.hexdigest()[:16]
 
 
